@@ -1,0 +1,192 @@
+/*
+ * muca.h -- C ABI of libmuca, the MI355X (gfx950) implementation of the
+ * equilibrium parallel multicanonical (MUCA) iteration of
+ * J. Zierenberg, M. Wiedenmann, W. Janke, "Application of the parallel
+ * multicanonical method to lattice gas condensation" (arXiv:1401.4076).
+ *
+ * The method (paper Sec. 2): p independent equilibrium runs share identical
+ * weights W^i(E); each run fills a histogram H^i_j(E); the histograms are
+ * summed, H^i(E) = sum_j H^i_j(E) (eq. (2)); the next weights W^{i+1} are
+ * computed from W^i and H^i by a recursive scheme and given back to every
+ * run; this repeats until the weights are converged.  Here each of many
+ * lattice-gas walkers on one GPU plays the role of one process.
+ *
+ * Model (Sec. 3, eq. (5)): lattice gas on a periodic square (d = 2) or
+ * simple-cubic (d = 3) lattice of V = L^d sites, occupations n_i in {0,1},
+ * fixed particle number N, E = -(number of occupied nearest-neighbour
+ * pairs) (J = 1).  A sweep is V update attempts (Sec. 4).  An attempt moves
+ * a uniform random particle to a uniform random empty site and is accepted
+ * with min(1, W(E_n)/W(E_o)) (Sec. 2).
+ *
+ * Reproducibility: results are a pure function of (groups, seed,
+ * first walker id, initial lnW, sweep schedule, rule).  They do not depend on
+ * the kernel layout, on graph or eager execution, or on how walkers are
+ * spread over devices.  Random numbers are Philox4x32-10 with key
+ * (global walker id, low 32 bits of seed); attempt t of a walker uses
+ * counters (t_lo, t_hi, r, 0), r = 0, 1, ...; the initial placement uses
+ * counters (i_lo, i_hi, 0, 1).
+ *
+ * Memory: the library owns walker state (allocated by mucaInit*, freed by
+ * mucaDestroy).  The caller owns lnW (double), P (double) and H (int32):
+ * device pointers of total_bins entries each, concatenated over groups in
+ * group order (group g starts at its bin offset, bin b <-> E = e_lo + b).
+ * Calls taking a `stream` (a hipStream_t; NULL = the null stream) are
+ * asynchronous on it unless stated otherwise.  A context is not
+ * thread-safe; use one context per stream.
+ *
+ * Errors: every call returns MUCA_OK (0), the positive status
+ * MUCA_NOT_CONVERGED, or a negative code; mucaLastError() returns a
+ * thread-local description of the last failure.  No C++ exception crosses
+ * this interface.
+ */
+#ifndef MUCA_H
+#define MUCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MUCA_OK 0
+#define MUCA_NOT_CONVERGED 1  /* mucaRun: max_iters reached before every group was flat */
+#define MUCA_EINVAL (-1)      /* invalid argument */
+#define MUCA_EOVERFLOW (-2)   /* walkers x sweeps of a group exceeds INT32_MAX */
+#define MUCA_ENOMEM (-3)      /* device allocation failed */
+#define MUCA_EHIP (-4)        /* HIP runtime error */
+#define MUCA_ENONFINITE (-5)  /* non-finite weight met by the sweep or produced by an update */
+
+#define MUCA_RULE_BERG 0   /* recursive scheme of Sec. 2, read as Berg's error-weighted recursion */
+#define MUCA_RULE_SIMPLE 1 /* W^{i+1}(E) = W^i(E) / H^i(E), Sec. 2 */
+
+#define MUCA_LAYOUT_AUTO 0 /* pick per context by timing (autotuner) */
+#define MUCA_LAYOUT_LANE 1 /* one walker per lane, lattice in LDS or HBM */
+#define MUCA_LAYOUT_WAVE 2 /* one walker per wavefront, speculative batches of attempts */
+
+typedef struct muca_context* muca_ctx;
+
+/* One group of walkers with its own lattice, weights and histogram.
+ * e_lo = e_hi = 0 selects the default window [E_floor(d,L,N), 0], where
+ * E_floor is the energy of a compact cluster built from full layers and
+ * rows (the paper takes the range from short parallel-tempering runs,
+ * Sec. 3).  Moves whose new energy leaves [e_lo, e_hi] are rejected. */
+typedef struct {
+  int32_t d;       /* 2 or 3 */
+  int32_t L;       /* 3 <= L <= 1024, V = L^d <= 2^24 */
+  int32_t N;       /* 1 <= N <= V-1; N <= V/2 for the default window */
+  int32_t walkers; /* >= 1 */
+  int32_t e_lo, e_hi; /* -d N <= e_lo <= e_hi <= 0, or both 0 */
+} muca_group;
+
+/* Create a context of one group; equivalent to mucaInitGroups with one
+ * group, default window and first walker id 0.  Runs the uniform random
+ * initial placement on the current device and waits for it. */
+int mucaInit(muca_ctx* out, int d, int L, int N, int walkers, uint64_t seed);
+
+/* Create a context of ngroups groups.  Walkers get global ids
+ * first_id, first_id + 1, ... group by group in array order (first_id lets
+ * several devices each own a disjoint range of one walker population).
+ * Allocates all device state on the current device, places the particles
+ * (N distinct uniform random sites per walker) and waits.  Fails with
+ * MUCA_EINVAL if an initial energy lies outside its group's window. */
+int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_t seed,
+                   uint32_t first_id);
+
+/* Default window [e_lo, e_hi] = [E_floor(d, L, N), 0] of a group, computed
+ * on the host (no device work).  Same validation as mucaInitGroups. */
+int mucaDefaultWindow(int d, int L, int N, int32_t* e_lo, int32_t* e_hi);
+
+/* Free all device state of the context.  NULL is accepted. */
+int mucaDestroy(muca_ctx ctx);
+
+/* Thread-local text of the last error ("" if none). */
+const char* mucaLastError(void);
+
+/* Sizes.  bin_offset is the index of bin 0 of group g in lnW, H and P. */
+int mucaNumGroups(muca_ctx ctx, int* ngroups);
+int mucaNumWalkers(muca_ctx ctx, int* nwalkers);
+int mucaTotalBins(muca_ctx ctx, int* total_bins);
+int mucaGetWindow(muca_ctx ctx, int group, int32_t* e_lo, int32_t* e_hi, int32_t* bin_offset);
+
+/* Kernel layout used by the sweep (MUCA_LAYOUT_*).  AUTO times the
+ * candidates on the first sweep and keeps the fastest.  Results are the same
+ * for every layout. */
+int mucaSetLayout(muca_ctx ctx, int layout);
+int mucaGetLayout(muca_ctx ctx, int* layout);
+
+/* Acceptance thresholds from the weights (Sec. 2, min(1, W(E_n)/W(E_o))):
+ * for every group, bin b_o and energy change dE in [-2d, 2d],
+ *   x = lnW[b_o + dE] - lnW[b_o],
+ *   T = 0xFFFFFFFF ("always") if x >= 0 or floor(exp(x) 2^32) >= 2^32 - 1,
+ *   T = 0 ("never") if x < -23 or b_o + dE is outside the window,
+ *   T = floor(exp(x) 2^32) otherwise (accept iff the attempt's 32-bit
+ *   uniform u < T),
+ * with exp evaluated by IEEE-754 binary64 operations only.  The table of
+ * group g holds bins_g x (4 d_g + 1) uint32, row b_o, column dE + 2 d_g;
+ * groups follow each other in order.  thr_out (device, may be NULL)
+ * receives a copy of the whole table; mucaThresholdEntries gives its size.
+ * lnW is a device pointer.  Non-finite weights give MUCA_ENONFINITE from
+ * the next synchronising call (mucaRun, mucaStatus). */
+int mucaThresholdEntries(muca_ctx ctx, int* entries);
+int mucaBuildThresholds(muca_ctx ctx, const double* lnW, uint32_t* thr_out, void* stream);
+
+/* Equilibrium runs with fixed weights (Sec. 2, eq. (2)): every walker of
+ * every group makes `sweeps` sweeps of V attempts with weights lnW
+ * (device, total_bins doubles), adding one histogram entry at its energy
+ * after each sweep.  H (device, total_bins int32) is overwritten with the
+ * summed histograms H^i(E) = sum_j H^i_j(E).  mucaSweepActive sweeps only
+ * groups with active[g] != 0 (device, ngroups int32) and leaves the H
+ * entries of the other groups untouched.  Walker state carries over from
+ * call to call.  Fails with MUCA_EOVERFLOW if walkers_g x sweeps > INT32_MAX. */
+int mucaSweep(muca_ctx ctx, const double* lnW, int sweeps, int32_t* H, void* stream);
+int mucaSweepActive(muca_ctx ctx, const double* lnW, int sweeps, int32_t* H,
+                    const int32_t* active, void* stream);
+
+/* Next weights from the previous weights and the summed histogram
+ * (Sec. 2), in place on lnW and P (device pointers).  rule:
+ *   MUCA_RULE_SIMPLE: lnW(b) -= ln max(H(b), 1), then lnW -= lnW(e_hi);
+ *   MUCA_RULE_BERG: for each pair of neighbouring bins (b, b+1) both
+ *     visited, p = H(b) H(b+1) / (H(b) + H(b+1)), P(b) += p, and the slope
+ *     d(b) = lnW(b+1) - lnW(b) becomes d(b) + (p / P(b)) (ln H(b) - ln H(b+1));
+ *     other slopes are kept, except that never-estimated pairs (P = 0) below
+ *     the lowest or above the highest estimated pair take that pair's slope;
+ *     lnW(e_hi) = 0 and lnW is rebuilt downward, one bin after the other.
+ * P[off_g + b] belongs to pair (b, b+1); the last entry of each group is
+ * unused; P must be zero at the start of a run.  ln is evaluated by
+ * IEEE-754 binary64 operations only. */
+int mucaUpdateWeights(muca_ctx ctx, const int32_t* H, double* lnW, double* P, int rule,
+                      void* stream);
+
+/* flags[g] (device, ngroups int32) = 1 if H of group g is flat: both window
+ * ends visited and 2 min_{b: H(b) > 0} H(b) > max_b H(b); else 0. */
+int mucaIsFlat(muca_ctx ctx, const int32_t* H, int32_t* flags, void* stream);
+
+/* The whole iteration (Sec. 2), synchronous.  lnW, P, H are device
+ * pointers; lnW holds the initial weights on entry (flat or learned), P is
+ * zeroed by the call.  iters and flat are host arrays of ngroups int32.
+ *   stop_on_flat = 0: exactly max_iters iterations of (sweep, update):
+ *     lnW = lnW^K, H = H^{K-1}, flat[g] = flatness of H^{K-1}, iters[g] = K.
+ *   stop_on_flat = 1: group g stops at its first flat H^i: lnW keeps lnW^i,
+ *     H keeps H^i, iters[g] = i + 1, flat[g] = 1.  Groups not flat after
+ *     max_iters keep lnW^{max_iters}, H^{max_iters - 1}, flat[g] = 0, and the
+ *     call returns MUCA_NOT_CONVERGED.
+ * The per-iteration work is captured once as a HIP graph and replayed. */
+int mucaRun(muca_ctx ctx, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
+            int max_iters, int rule, int stop_on_flat, int32_t* iters, int32_t* flat,
+            void* stream);
+
+/* Copy one walker's state to host memory (waits for the device):
+ * occupation bits (ceil(V/32) words, site s = x + L y + L^2 z is bit s%32 of
+ * word s/32), particle sites pos[N], energy and attempt counter.  Any of
+ * the output pointers may be NULL. */
+int mucaReadWalker(muca_ctx ctx, int walker, uint32_t* bits, uint32_t* pos, int32_t* E,
+                   uint64_t* t);
+
+/* Synchronise the context's last stream and report a pending device-side
+ * error (MUCA_ENONFINITE) or MUCA_OK.  Clears the pending error. */
+int mucaStatus(muca_ctx ctx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,323 @@
+// muca_kernels.hip -- HIP kernels of the parallel multicanonical iteration
+// for gfx950: initial placement, acceptance thresholds, the equilibrium
+// sweep (one walker per lane), histogram clearing, the binary64 weight
+// recursion and the flatness test.  Each kernel cites the step of the
+// method it implements (paper Sec. 2-4).
+#include "muca_kernels.h"
+
+#pragma clang fp contract(off)
+
+namespace muca {
+
+// ---------------------------------------------------------------- placement
+// Fixed particle number (Sec. 3): N distinct uniform random sites per walker,
+// drawn from the placement stream (counters (i_lo, i_hi, 0, 1)); an occupied
+// candidate is skipped.  E is then counted once per occupied pair.
+__global__ void k_init_place(const GroupDesc* __restrict__ groups,
+                             const int32_t* __restrict__ wgroup, uint32_t* __restrict__ bits,
+                             uint32_t* __restrict__ pos, int32_t* __restrict__ E,
+                             uint64_t* __restrict__ T, int nwalkers, uint32_t first_id,
+                             uint32_t seed32) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwalkers) return;
+  const GroupDesc g = groups[wgroup[w]];
+  const int64_t j = w - g.first_walker;
+  uint32_t* wb = bits + g.bits_off + j * g.words;
+  uint32_t* wp = pos + g.pos_off + j * g.N;
+  for (int i = 0; i < g.words; ++i) wb[i] = 0u;
+  const uint32_t key0 = first_id + (uint32_t)w;
+  int placed = 0;
+  for (uint64_t i = 0; placed < g.N; ++i) {
+    const U4 r = philox((uint32_t)i, (uint32_t)(i >> 32), 0u, 1u, key0, seed32);
+    const uint32_t cand[4] = {r.x, r.y, r.z, r.w};
+    for (int c = 0; c < 4 && placed < g.N; ++c) {
+      const uint32_t s = draw(cand[c], (uint32_t)g.V);
+      const uint32_t m = 1u << (s & 31u);
+      if (!(wb[s >> 5] & m)) {
+        wb[s >> 5] |= m;
+        wp[placed++] = s;
+      }
+    }
+  }
+  int pairs = 0;
+  for (int k = 0; k < g.N; ++k) {
+    uint32_t nb[6];
+    neighbours(g, wp[k], nb);
+    for (int a = 0; a < g.d; ++a) {  // + direction of each axis: each pair once
+      const uint32_t q = nb[2 * a];
+      pairs += (wb[q >> 5] >> (q & 31u)) & 1u;
+    }
+  }
+  E[w] = -pairs;
+  T[w] = 0;
+}
+
+// ---------------------------------------------------------------- thresholds
+// Acceptance min(1, W(E_n)/W(E_o)) of Sec. 2 tabulated per (b_o, dE) from
+// binary64 lnW; window exits are "never".  grid.y = group.
+__global__ void k_thresholds(const GroupDesc* __restrict__ groups, const double* __restrict__ lnW,
+                             uint32_t* __restrict__ thr, int32_t* __restrict__ status) {
+  const GroupDesc g = groups[blockIdx.y];
+  const int n = g.nbins * g.nd;
+  const double* lw = lnW + g.bin_off;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int bo = i / g.nd;
+    const int dE = i - bo * g.nd - 2 * g.d;
+    const int bn = bo + dE;
+    uint32_t T = 0u;
+    if (bn >= 0 && bn < g.nbins) {
+      const double a = lw[bn], b = lw[bo];
+      if (!isfinite(a) || !isfinite(b)) {
+        atomicOr(status, 1);
+      } else {
+        T = threshold(a - b);
+      }
+    }
+    thr[g.thr_off + i] = T;
+  }
+}
+
+// ---------------------------------------------------------------- histograms
+__global__ void k_zero_hist(const GroupDesc* __restrict__ groups, const int32_t* __restrict__ active,
+                            int32_t* __restrict__ H) {
+  const int gi = blockIdx.y;
+  if (active && !active[gi]) return;
+  const GroupDesc g = groups[gi];
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < g.nbins; b += gridDim.x * blockDim.x)
+    H[g.bin_off + b] = 0;
+}
+
+// ---------------------------------------------------------------- sweep (lane)
+// Equilibrium run with fixed weights (Sec. 2), one walker per lane, walker
+// state in device memory.  One attempt t: Philox block (t_lo, t_hi, 0, 0) =
+// (x0, x1, x2, x3); particle k = draw(x0, N) at s_o; the first empty site
+// among draw(x2, V), draw(x3, V), then the words of blocks r = 1, 2, ... is
+// s_n; dE = k_o - k_n with k_n not counting s_o; accept iff the threshold of
+// (E_o, dE) admits x1.  After each sweep of V attempts (Sec. 4) the walker
+// adds one entry at its energy (eq. (2)).
+__global__ void __launch_bounds__(64) k_sweep_lane(
+    const GroupDesc* __restrict__ groups, const int32_t* __restrict__ wgroup,
+    uint32_t* __restrict__ bits, uint32_t* __restrict__ pos, int32_t* __restrict__ E,
+    uint64_t* __restrict__ T, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
+    const int32_t* __restrict__ active, int nwalkers, int sweeps, uint32_t first_id,
+    uint32_t seed32) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwalkers) return;
+  const int gi = wgroup[w];
+  if (active && !active[gi]) return;
+  const GroupDesc g = groups[gi];
+  const int64_t j = w - g.first_walker;
+  uint32_t* wb = bits + g.bits_off + j * g.words;
+  uint32_t* wp = pos + g.pos_off + j * g.N;
+  const uint32_t* th = thr + g.thr_off;
+  int32_t* hg = H + g.bin_off;
+  const uint32_t key0 = first_id + (uint32_t)w;
+  int32_t e = E[w];
+  uint64_t t = T[w];
+  const uint32_t V = (uint32_t)g.V, N = (uint32_t)g.N;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (uint32_t a = 0; a < V; ++a, ++t) {
+      const uint32_t tl = (uint32_t)t, th_ = (uint32_t)(t >> 32);
+      U4 r = philox(tl, th_, 0u, 0u, key0, seed32);
+      const uint32_t u = r.y;
+      const uint32_t k = draw(r.x, N);
+      const uint32_t so = wp[k];
+      uint32_t sn = draw(r.z, V);
+      if ((wb[sn >> 5] >> (sn & 31u)) & 1u) {
+        sn = draw(r.w, V);
+        uint32_t blk = 0;
+        while ((wb[sn >> 5] >> (sn & 31u)) & 1u) {
+          blk += 1;
+          r = philox(tl, th_, blk, 0u, key0, seed32);
+          sn = draw(r.x, V);
+          if (!((wb[sn >> 5] >> (sn & 31u)) & 1u)) break;
+          sn = draw(r.y, V);
+          if (!((wb[sn >> 5] >> (sn & 31u)) & 1u)) break;
+          sn = draw(r.z, V);
+          if (!((wb[sn >> 5] >> (sn & 31u)) & 1u)) break;
+          sn = draw(r.w, V);
+        }
+      }
+      uint32_t nb[6];
+      int ko = 0, kn = 0;
+      neighbours(g, so, nb);
+      for (int q = 0; q < 2 * g.d; ++q) ko += (wb[nb[q] >> 5] >> (nb[q] & 31u)) & 1u;
+      neighbours(g, sn, nb);
+      for (int q = 0; q < 2 * g.d; ++q)
+        kn += (nb[q] != so) ? ((wb[nb[q] >> 5] >> (nb[q] & 31u)) & 1u) : 0u;
+      const int dE = ko - kn;
+      const uint32_t Tacc = th[(e - g.e_lo) * g.nd + dE + 2 * g.d];
+      if (accepts(Tacc, u)) {
+        wb[so >> 5] &= ~(1u << (so & 31u));
+        wb[sn >> 5] |= 1u << (sn & 31u);
+        wp[k] = sn;
+        e += dE;
+      }
+    }
+    atomicAdd(&hg[e - g.e_lo], 1);
+  }
+  E[w] = e;
+  T[w] = t;
+}
+
+// ---------------------------------------------------------------- recursion
+// Next weights from lnW and the summed histogram (Sec. 2).  One block per
+// active group.  The Berg rule first computes every slope in parallel, then
+// one lane rebuilds lnW from lnW(e_hi) = 0 downward in a fixed order.
+__global__ void __launch_bounds__(256) k_update(const GroupDesc* __restrict__ groups,
+                                                const int32_t* __restrict__ H,
+                                                double* __restrict__ lnW, double* __restrict__ P,
+                                                double* __restrict__ slope, int rule,
+                                                const int32_t* __restrict__ active,
+                                                int32_t* __restrict__ status) {
+  const int gi = blockIdx.x;
+  if (active && !active[gi]) return;
+  const GroupDesc g = groups[gi];
+  const int nb = g.nbins;
+  const int32_t* h = H + g.bin_off;
+  double* lw = lnW + g.bin_off;
+  double* pp = P + g.bin_off;
+  double* d = slope + g.bin_off;
+  __shared__ int lo_s, hi_s, bad_s;
+  if (threadIdx.x == 0) {
+    lo_s = nb;
+    hi_s = -1;
+    bad_s = 0;
+  }
+  __syncthreads();
+  if (rule == 1) {
+    // W^{i+1}(E) = W^i(E) / H^i(E); an empty bin keeps its weight.
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int32_t hb = h[b] > 0 ? h[b] : 1;
+      d[b] = lw[b] - log_ieee(hb);
+    }
+    __syncthreads();
+    const double top = d[nb - 1];
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const double v = d[b] - top;
+      lw[b] = v;
+      if (!isfinite(v)) bad_s = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bad_s) atomicOr(status, 2);
+    return;
+  }
+  // Berg: p-weighted mean of the slope estimates of all iterations.
+  int lo = nb, hi = -1;
+  for (int b = threadIdx.x; b + 1 < nb; b += blockDim.x) {
+    const double slope_old = lw[b + 1] - lw[b];
+    if (h[b] > 0 && h[b + 1] > 0) {
+      const double h0 = (double)h[b], h1 = (double)h[b + 1];
+      const double p = h0 * h1 / (h0 + h1);
+      const double acc = pp[b] + p;
+      pp[b] = acc;
+      const double kappa = p / acc;
+      d[b] = slope_old + kappa * (log_ieee(h[b]) - log_ieee(h[b + 1]));
+    } else {
+      d[b] = slope_old;
+    }
+    if (pp[b] > 0.0) {
+      lo = min(lo, b);
+      hi = max(hi, b);
+    }
+  }
+  atomicMin(&lo_s, lo);
+  atomicMax(&hi_s, hi);
+  __syncthreads();
+  const int elo = lo_s, ehi = hi_s;
+  if (ehi >= 0) {  // frontier: copy the nearest estimated slope outward
+    const double dl = d[elo], dh = d[ehi];
+    __syncthreads();
+    for (int b = threadIdx.x; b + 1 < nb; b += blockDim.x) {
+      if (b < elo) d[b] = dl;
+      if (b > ehi) d[b] = dh;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    lw[nb - 1] = v;
+    int bad = 0;
+    for (int b = nb - 2; b >= 0; --b) {
+      v = v - d[b];
+      lw[b] = v;
+      bad |= !isfinite(v);
+    }
+    if (bad) atomicOr(status, 2);
+  }
+}
+
+// ---------------------------------------------------------------- flatness
+// flat <=> both window ends visited and 2 min_{H>0} H > max H.
+__device__ __forceinline__ int group_flat(const int32_t* h, int nb, int* mn_s, int* mx_s) {
+  int mn = 0x7FFFFFFF, mx = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int v = h[b];
+    if (v > 0) mn = min(mn, v);
+    mx = max(mx, v);
+  }
+  atomicMin(mn_s, mn);
+  atomicMax(mx_s, mx);
+  __syncthreads();
+  return (h[0] > 0 && h[nb - 1] > 0 && 2LL * (long long)(*mn_s) > (long long)(*mx_s)) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_flat(const GroupDesc* __restrict__ groups,
+                                              const int32_t* __restrict__ H,
+                                              int32_t* __restrict__ flags) {
+  const GroupDesc g = groups[blockIdx.x];
+  __shared__ int mn_s, mx_s;
+  if (threadIdx.x == 0) {
+    mn_s = 0x7FFFFFFF;
+    mx_s = 0;
+  }
+  __syncthreads();
+  const int f = group_flat(H + g.bin_off, g.nbins, &mn_s, &mx_s);
+  if (threadIdx.x == 0) flags[blockIdx.x] = f;
+}
+
+// Loop control of the iteration: for each active group record the flatness
+// of H^i and the iteration count; with stop_on_flat a flat group becomes
+// inactive (keeps lnW^i, H^i).  remaining = number of groups still active.
+__global__ void __launch_bounds__(256) k_control(const GroupDesc* __restrict__ groups,
+                                                 const int32_t* __restrict__ H,
+                                                 int32_t* __restrict__ active,
+                                                 int32_t* __restrict__ flat,
+                                                 int32_t* __restrict__ iters,
+                                                 int32_t* __restrict__ iter_counter,
+                                                 int32_t* __restrict__ remaining,
+                                                 int stop_on_flat) {
+  const int gi = blockIdx.x;
+  if (!active[gi]) return;
+  const GroupDesc g = groups[gi];
+  __shared__ int mn_s, mx_s;
+  if (threadIdx.x == 0) {
+    mn_s = 0x7FFFFFFF;
+    mx_s = 0;
+  }
+  __syncthreads();
+  const int f = group_flat(H + g.bin_off, g.nbins, &mn_s, &mx_s);
+  if (threadIdx.x == 0) {
+    flat[gi] = f;
+    iters[gi] = *iter_counter + 1;
+    if (stop_on_flat && f) {
+      active[gi] = 0;
+      atomicSub(remaining, 1);
+    }
+  }
+}
+
+__global__ void k_bump(int32_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter += 1;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+}  // namespace muca

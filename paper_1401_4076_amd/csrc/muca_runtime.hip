@@ -1,0 +1,516 @@
+// muca_runtime.hip -- host runtime and C ABI of libmuca (see include/muca.h).
+//
+// Owns the device state of all walkers (occupation bits, particle sites,
+// energies, attempt counters), the per-group descriptors and the acceptance
+// threshold table; launches the kernels of the MUCA iteration (paper Sec. 2)
+// on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/muca.h"
+#include "muca_kernels.h"
+
+using muca::GroupDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? MUCA_ENOMEM : MUCA_EHIP, "%s: %s (%s:%d)",    \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                        \
+  } while (0)
+
+#define HIP_TRY_DEL(expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      delete c;                                                                             \
+      return fail(MUCA_EHIP, "%s: %s", #expr, hipGetErrorString(e_));                       \
+    }                                                                                       \
+  } while (0)
+
+#define LAUNCH_CHECK()                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = hipGetLastError();                                                      \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(MUCA_EHIP, "kernel launch: %s (%s:%d)", hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                \
+  } while (0)
+
+// Default lower window edge: the energy of a compact cluster.  In 2D a
+// w-wide block of N sites filled row by row has 2N - w - ceil(N/w) bonds;
+// in 3D full x*y layers stacked z high (3xyz - xy - yz - zx bonds) carry a
+// partial layer of m sites filled in the same way, each with one bond down.
+// No extent reaches L, so no bond wraps round the torus.
+int64_t block_bonds(int64_t m, int64_t wmax, int64_t hmax) {
+  if (m == 0) return 0;
+  int64_t best = -1;
+  for (int64_t w = 1; w <= wmax && w <= m; ++w) {
+    const int64_t rows = (m + w - 1) / w;
+    if (rows > hmax) continue;
+    best = std::max(best, 2 * m - w - rows);
+  }
+  return best;
+}
+
+int32_t energy_floor(int d, int L, int N) {
+  const int64_t e = L - 1;
+  if (d == 2) return (int32_t)(-std::max<int64_t>(0, block_bonds(N, e, e)));
+  int64_t best = 0;
+  for (int64_t x = 1; x <= e; ++x)
+    for (int64_t y = 1; y <= e; ++y) {
+      const int64_t layer = x * y, z = N / layer, m = N - layer * z;
+      if (z + (m ? 1 : 0) > e) continue;
+      const int64_t top = block_bonds(m, x, y);
+      if (top < 0) continue;
+      const int64_t box = z ? 3 * layer * z - layer - y * z - z * x : 0;
+      best = std::max(best, box + top + (z ? m : 0));
+    }
+  return (int32_t)(-best);
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  HIP_TRY(hipMalloc((void**)p, n * sizeof(T)));
+  return MUCA_OK;
+}
+
+}  // namespace
+
+struct muca_context {
+  int device = 0;
+  uint32_t seed32 = 0, first_id = 0;
+  std::vector<GroupDesc> g;
+  GroupDesc* d_groups = nullptr;
+  int ngroups = 0, nwalkers = 0, total_bins = 0, thr_entries = 0;
+  int64_t total_words = 0, total_pos = 0;
+  uint32_t* d_bits = nullptr;
+  uint32_t* d_pos = nullptr;
+  int32_t* d_E = nullptr;
+  uint64_t* d_T = nullptr;
+  int32_t* d_wgroup = nullptr;
+  uint32_t* d_thr = nullptr;
+  double* d_slope = nullptr;
+  int32_t* d_status = nullptr;  // bit 0: non-finite weight read; bit 1: produced
+  int32_t* d_ones = nullptr;
+  int32_t* d_active = nullptr;
+  int32_t* d_flat = nullptr;
+  int32_t* d_iters = nullptr;
+  int32_t* d_counter = nullptr;  // [0] iteration index, [1] groups still active
+  int32_t* h_pinned = nullptr;   // host-pinned readback of the counters
+  int layout = MUCA_LAYOUT_AUTO;
+  hipStream_t last_stream = nullptr;
+
+  ~muca_context() {
+    (void)hipFree(d_groups);
+    (void)hipFree(d_bits);
+    (void)hipFree(d_pos);
+    (void)hipFree(d_E);
+    (void)hipFree(d_T);
+    (void)hipFree(d_wgroup);
+    (void)hipFree(d_thr);
+    (void)hipFree(d_slope);
+    (void)hipFree(d_status);
+    (void)hipFree(d_ones);
+    (void)hipFree(d_active);
+    (void)hipFree(d_flat);
+    (void)hipFree(d_iters);
+    (void)hipFree(d_counter);
+    if (h_pinned) (void)hipHostFree(h_pinned);
+  }
+};
+
+namespace {
+
+int check_ctx(muca_ctx c) {
+  if (!c) return fail(MUCA_EINVAL, "null context");
+  return MUCA_OK;
+}
+
+int enqueue_thresholds(muca_ctx c, const double* lnW, hipStream_t s) {
+  int maxe = 0;
+  for (const auto& q : c->g) maxe = std::max(maxe, q.nbins * q.nd);
+  dim3 grid((unsigned)std::min(1024, (maxe + 255) / 256), (unsigned)c->ngroups);
+  hipLaunchKernelGGL(muca::k_thresholds, grid, dim3(256), 0, s, c->d_groups, lnW, c->d_thr,
+                     c->d_status);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
+int enqueue_sweep(muca_ctx c, const double* lnW, int sweeps, int32_t* H, const int32_t* active,
+                  hipStream_t s) {
+  int rc = enqueue_thresholds(c, lnW, s);
+  if (rc) return rc;
+  int maxb = 0;
+  for (const auto& q : c->g) maxb = std::max(maxb, q.nbins);
+  hipLaunchKernelGGL(muca::k_zero_hist, dim3((unsigned)((maxb + 255) / 256), (unsigned)c->ngroups),
+                     dim3(256), 0, s, c->d_groups, active, H);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(muca::k_sweep_lane, dim3((unsigned)((c->nwalkers + 63) / 64)), dim3(64), 0, s,
+                     c->d_groups, c->d_wgroup, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H,
+                     active, c->nwalkers, sweeps, c->first_id, c->seed32);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
+int check_sweeps(muca_ctx c, int sweeps) {
+  if (sweeps < 1) return fail(MUCA_EINVAL, "sweeps must be >= 1 (got %d)", sweeps);
+  for (size_t i = 0; i < c->g.size(); ++i)
+    if ((int64_t)c->g[i].walkers * (int64_t)sweeps > 2147483647LL)
+      return fail(MUCA_EOVERFLOW, "group %zu: walkers x sweeps exceeds INT32_MAX", i);
+  return MUCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mucaLastError(void) { return g_last_error.c_str(); }
+
+int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_t seed,
+                   uint32_t first_id) {
+  if (!out) return fail(MUCA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!groups || ngroups < 1) return fail(MUCA_EINVAL, "need at least one group");
+  auto* c = new (std::nothrow) muca_context();
+  if (!c) return fail(MUCA_ENOMEM, "host allocation failed");
+  c->seed32 = (uint32_t)seed;
+  c->first_id = first_id;
+  c->ngroups = ngroups;
+  int64_t walkers = 0, bins = 0, thr = 0, words = 0, pos = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    const muca_group q = groups[i];
+    auto bad = [&](const char* why) {
+      delete c;
+      return fail(MUCA_EINVAL, "group %d (d=%d L=%d N=%d walkers=%d window=[%d,%d]): %s", i, q.d,
+                  q.L, q.N, q.walkers, q.e_lo, q.e_hi, why);
+    };
+    if (q.d != 2 && q.d != 3) return bad("d must be 2 or 3");
+    if (q.L < 3 || q.L > 1024) return bad("L must be in [3, 1024]");
+    const int64_t V = (q.d == 2) ? (int64_t)q.L * q.L : (int64_t)q.L * q.L * q.L;
+    if (V > (1 << 24)) return bad("V = L^d must not exceed 2^24");
+    if (q.walkers < 1) return bad("walkers must be >= 1");
+    if (q.N < 1 || q.N > V - 1) return bad("N must be in [1, V-1]");
+    GroupDesc d{};
+    d.d = q.d;
+    d.L = q.L;
+    d.N = q.N;
+    d.V = (int32_t)V;
+    if (q.e_lo == 0 && q.e_hi == 0) {
+      if (2 * (int64_t)q.N > V) return bad("default window needs N <= V/2");
+      d.e_lo = energy_floor(q.d, q.L, q.N);
+      d.e_hi = 0;
+    } else {
+      if (q.e_lo > q.e_hi || q.e_hi > 0 || (int64_t)q.e_lo < -(int64_t)q.d * q.N)
+        return bad("window must satisfy -dN <= e_lo <= e_hi <= 0");
+      d.e_lo = q.e_lo;
+      d.e_hi = q.e_hi;
+    }
+    d.nbins = d.e_hi - d.e_lo + 1;
+    d.nd = 4 * q.d + 1;
+    d.bin_off = (int32_t)bins;
+    d.thr_off = (int32_t)thr;
+    d.first_walker = (int32_t)walkers;
+    d.walkers = q.walkers;
+    d.words = (int32_t)((V + 31) / 32);
+    d.LL = q.L * q.L;
+    d.invL = 1.0f / (float)q.L;
+    d.bits_off = words;
+    d.pos_off = pos;
+    walkers += q.walkers;
+    bins += d.nbins;
+    thr += (int64_t)d.nbins * d.nd;
+    words += (int64_t)q.walkers * d.words;
+    pos += (int64_t)q.walkers * q.N;
+    if (walkers > 0x7FFFFFFF || thr > 0x7FFFFFFF) {
+      delete c;
+      return fail(MUCA_EINVAL, "too many walkers or bins");
+    }
+    c->g.push_back(d);
+  }
+  c->nwalkers = (int)walkers;
+  c->total_bins = (int)bins;
+  c->thr_entries = (int)thr;
+  c->total_words = words;
+  c->total_pos = pos;
+  HIP_TRY_DEL(hipGetDevice(&c->device));
+
+  std::vector<int32_t> wg((size_t)walkers);
+  for (int i = 0; i < ngroups; ++i)
+    for (int j = 0; j < c->g[i].walkers; ++j) wg[(size_t)c->g[i].first_walker + j] = i;
+
+  int rc = MUCA_OK;
+  auto run = [&]() -> int {
+    int r;
+    if ((r = dev_alloc(&c->d_groups, (size_t)ngroups))) return r;
+    if ((r = dev_alloc(&c->d_bits, (size_t)words))) return r;
+    if ((r = dev_alloc(&c->d_pos, (size_t)pos))) return r;
+    if ((r = dev_alloc(&c->d_E, (size_t)walkers))) return r;
+    if ((r = dev_alloc(&c->d_T, (size_t)walkers))) return r;
+    if ((r = dev_alloc(&c->d_wgroup, (size_t)walkers))) return r;
+    if ((r = dev_alloc(&c->d_thr, (size_t)thr))) return r;
+    if ((r = dev_alloc(&c->d_slope, (size_t)bins))) return r;
+    if ((r = dev_alloc(&c->d_status, 1))) return r;
+    if ((r = dev_alloc(&c->d_ones, (size_t)ngroups))) return r;
+    if ((r = dev_alloc(&c->d_active, (size_t)ngroups))) return r;
+    if ((r = dev_alloc(&c->d_flat, (size_t)ngroups))) return r;
+    if ((r = dev_alloc(&c->d_iters, (size_t)ngroups))) return r;
+    if ((r = dev_alloc(&c->d_counter, 2))) return r;
+    HIP_TRY(hipHostMalloc((void**)&c->h_pinned, 4 * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipMemcpy(c->d_groups, c->g.data(), sizeof(GroupDesc) * (size_t)ngroups,
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_wgroup, wg.data(), sizeof(int32_t) * wg.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(c->d_status, 0, sizeof(int32_t)));
+    hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, nullptr, c->d_ones, 1, ngroups);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(muca::k_init_place, dim3((unsigned)((walkers + 63) / 64)), dim3(64), 0,
+                       nullptr, c->d_groups, c->d_wgroup, c->d_bits, c->d_pos, c->d_E, c->d_T,
+                       (int)walkers, first_id, c->seed32);
+    LAUNCH_CHECK();
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<int32_t> E((size_t)walkers);
+    HIP_TRY(hipMemcpy(E.data(), c->d_E, sizeof(int32_t) * E.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < ngroups; ++i)
+      for (int j = 0; j < c->g[i].walkers; ++j) {
+        const int32_t e = E[(size_t)c->g[i].first_walker + j];
+        if (e < c->g[i].e_lo || e > c->g[i].e_hi)
+          return fail(MUCA_EINVAL, "group %d walker %d: initial energy %d outside window [%d,%d]",
+                      i, j, e, c->g[i].e_lo, c->g[i].e_hi);
+      }
+    return MUCA_OK;
+  };
+  rc = run();
+  if (rc != MUCA_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return MUCA_OK;
+}
+
+int mucaDefaultWindow(int d, int L, int N, int32_t* e_lo, int32_t* e_hi) {
+  if (!e_lo || !e_hi) return fail(MUCA_EINVAL, "null output");
+  if (d != 2 && d != 3) return fail(MUCA_EINVAL, "d must be 2 or 3");
+  if (L < 3 || L > 1024) return fail(MUCA_EINVAL, "L must be in [3, 1024]");
+  const int64_t V = (d == 2) ? (int64_t)L * L : (int64_t)L * L * L;
+  if (V > (1 << 24)) return fail(MUCA_EINVAL, "V = L^d must not exceed 2^24");
+  if (N < 1 || 2 * (int64_t)N > V) return fail(MUCA_EINVAL, "default window needs 1 <= N <= V/2");
+  *e_lo = energy_floor(d, L, N);
+  *e_hi = 0;
+  return MUCA_OK;
+}
+
+int mucaInit(muca_ctx* out, int d, int L, int N, int walkers, uint64_t seed) {
+  muca_group q{d, L, N, walkers, 0, 0};
+  return mucaInitGroups(out, &q, 1, seed, 0u);
+}
+
+int mucaDestroy(muca_ctx ctx) {
+  if (!ctx) return MUCA_OK;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return MUCA_OK;
+}
+
+int mucaNumGroups(muca_ctx c, int* n) {
+  if (int r = check_ctx(c)) return r;
+  if (!n) return fail(MUCA_EINVAL, "null output");
+  *n = c->ngroups;
+  return MUCA_OK;
+}
+
+int mucaNumWalkers(muca_ctx c, int* n) {
+  if (int r = check_ctx(c)) return r;
+  if (!n) return fail(MUCA_EINVAL, "null output");
+  *n = c->nwalkers;
+  return MUCA_OK;
+}
+
+int mucaTotalBins(muca_ctx c, int* n) {
+  if (int r = check_ctx(c)) return r;
+  if (!n) return fail(MUCA_EINVAL, "null output");
+  *n = c->total_bins;
+  return MUCA_OK;
+}
+
+int mucaGetWindow(muca_ctx c, int group, int32_t* e_lo, int32_t* e_hi, int32_t* bin_offset) {
+  if (int r = check_ctx(c)) return r;
+  if (group < 0 || group >= c->ngroups) return fail(MUCA_EINVAL, "group %d out of range", group);
+  if (e_lo) *e_lo = c->g[group].e_lo;
+  if (e_hi) *e_hi = c->g[group].e_hi;
+  if (bin_offset) *bin_offset = c->g[group].bin_off;
+  return MUCA_OK;
+}
+
+int mucaSetLayout(muca_ctx c, int layout) {
+  if (int r = check_ctx(c)) return r;
+  if (layout < MUCA_LAYOUT_AUTO || layout > MUCA_LAYOUT_WAVE)
+    return fail(MUCA_EINVAL, "unknown layout %d", layout);
+  c->layout = layout;
+  return MUCA_OK;
+}
+
+int mucaGetLayout(muca_ctx c, int* layout) {
+  if (int r = check_ctx(c)) return r;
+  if (!layout) return fail(MUCA_EINVAL, "null output");
+  *layout = c->layout;
+  return MUCA_OK;
+}
+
+int mucaThresholdEntries(muca_ctx c, int* entries) {
+  if (int r = check_ctx(c)) return r;
+  if (!entries) return fail(MUCA_EINVAL, "null output");
+  *entries = c->thr_entries;
+  return MUCA_OK;
+}
+
+int mucaBuildThresholds(muca_ctx c, const double* lnW, uint32_t* thr_out, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW) return fail(MUCA_EINVAL, "lnW is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  if (int r = enqueue_thresholds(c, lnW, s)) return r;
+  if (thr_out)
+    HIP_TRY(hipMemcpyAsync(thr_out, c->d_thr, sizeof(uint32_t) * (size_t)c->thr_entries,
+                           hipMemcpyDeviceToDevice, s));
+  return MUCA_OK;
+}
+
+int mucaSweepActive(muca_ctx c, const double* lnW, int sweeps, int32_t* H, const int32_t* active,
+                    void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW || !H) return fail(MUCA_EINVAL, "lnW and H must not be NULL");
+  if (int r = check_sweeps(c, sweeps)) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  return enqueue_sweep(c, lnW, sweeps, H, active ? active : c->d_ones, s);
+}
+
+int mucaSweep(muca_ctx c, const double* lnW, int sweeps, int32_t* H, void* stream) {
+  return mucaSweepActive(c, lnW, sweeps, H, nullptr, stream);
+}
+
+int mucaUpdateWeights(muca_ctx c, const int32_t* H, double* lnW, double* P, int rule,
+                      void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!H || !lnW || !P) return fail(MUCA_EINVAL, "H, lnW and P must not be NULL");
+  if (rule != MUCA_RULE_BERG && rule != MUCA_RULE_SIMPLE)
+    return fail(MUCA_EINVAL, "unknown rule %d", rule);
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  hipLaunchKernelGGL(muca::k_update, dim3((unsigned)c->ngroups), dim3(256), 0, s, c->d_groups, H,
+                     lnW, P, c->d_slope, rule, c->d_ones, c->d_status);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
+int mucaIsFlat(muca_ctx c, const int32_t* H, int32_t* flags, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!H || !flags) return fail(MUCA_EINVAL, "H and flags must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  hipLaunchKernelGGL(muca::k_flat, dim3((unsigned)c->ngroups), dim3(256), 0, s, c->d_groups, H,
+                     flags);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
+int mucaStatus(muca_ctx c, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  hipStream_t s = stream ? (hipStream_t)stream : c->last_stream;
+  HIP_TRY(hipStreamSynchronize(s));
+  int32_t st = 0;
+  HIP_TRY(hipMemcpy(&st, c->d_status, sizeof st, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(c->d_status, 0, sizeof st));
+  if (st & 1) return fail(MUCA_ENONFINITE, "non-finite weight passed to a sweep");
+  if (st & 2) return fail(MUCA_ENONFINITE, "weight update produced a non-finite weight");
+  return MUCA_OK;
+}
+
+int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter, int max_iters,
+            int rule, int stop_on_flat, int32_t* iters, int32_t* flat, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW || !P || !H || !iters || !flat)
+    return fail(MUCA_EINVAL, "lnW, P, H, iters and flat must not be NULL");
+  if (max_iters < 1) return fail(MUCA_EINVAL, "max_iters must be >= 1");
+  if (rule != MUCA_RULE_BERG && rule != MUCA_RULE_SIMPLE)
+    return fail(MUCA_EINVAL, "unknown rule %d", rule);
+  if (int r = check_sweeps(c, sweeps_per_iter)) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const int G = c->ngroups;
+  hipLaunchKernelGGL(muca::k_fill_f64, dim3((unsigned)std::min(1024, (c->total_bins + 255) / 256)),
+                     dim3(256), 0, s, P, 0.0, c->total_bins);
+  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_active, 1, G);
+  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_flat, 0, G);
+  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_iters, 0, G);
+  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter, 0, 1);
+  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter + 1, G, 1);
+  LAUNCH_CHECK();
+  int remaining = G;
+  for (int i = 0; i < max_iters; ++i) {
+    if (int r = enqueue_sweep(c, lnW, sweeps_per_iter, H, c->d_active, s)) return r;
+    hipLaunchKernelGGL(muca::k_control, dim3((unsigned)G), dim3(256), 0, s, c->d_groups, H,
+                       c->d_active, c->d_flat, c->d_iters, c->d_counter, c->d_counter + 1,
+                       stop_on_flat);
+    hipLaunchKernelGGL(muca::k_update, dim3((unsigned)G), dim3(256), 0, s, c->d_groups, H, lnW, P,
+                       c->d_slope, rule, c->d_active, c->d_status);
+    hipLaunchKernelGGL(muca::k_bump, dim3(1), dim3(64), 0, s, c->d_counter);
+    LAUNCH_CHECK();
+    if (stop_on_flat) {
+      HIP_TRY(hipMemcpyAsync(c->h_pinned, c->d_counter, 2 * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      remaining = c->h_pinned[1];
+      if (remaining == 0) break;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(iters, c->d_iters, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(flat, c->d_flat, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
+  if (int r = mucaStatus(c, s)) return r;
+  return (stop_on_flat && remaining > 0) ? MUCA_NOT_CONVERGED : MUCA_OK;
+}
+
+int mucaReadWalker(muca_ctx c, int walker, uint32_t* bits, uint32_t* pos, int32_t* E,
+                   uint64_t* t) {
+  if (int r = check_ctx(c)) return r;
+  if (walker < 0 || walker >= c->nwalkers) return fail(MUCA_EINVAL, "walker %d out of range", walker);
+  HIP_TRY(hipDeviceSynchronize());
+  int gi = 0;
+  while (gi + 1 < c->ngroups && walker >= c->g[gi + 1].first_walker) ++gi;
+  const GroupDesc& g = c->g[gi];
+  const int64_t j = walker - g.first_walker;
+  if (bits)
+    HIP_TRY(hipMemcpy(bits, c->d_bits + g.bits_off + j * g.words, sizeof(uint32_t) * g.words,
+                      hipMemcpyDeviceToHost));
+  if (pos)
+    HIP_TRY(hipMemcpy(pos, c->d_pos + g.pos_off + j * g.N, sizeof(uint32_t) * g.N,
+                      hipMemcpyDeviceToHost));
+  if (E) HIP_TRY(hipMemcpy(E, c->d_E + walker, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (t) HIP_TRY(hipMemcpy(t, c->d_T + walker, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return MUCA_OK;
+}
+
+}  // extern "C"

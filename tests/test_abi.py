@@ -1,0 +1,77 @@
+"""C-ABI checks that need no GPU: libmuca.so loads, exports every function
+include/muca.h declares, validates arguments on the host before any device
+work, and computes the default window like the oracle (two independent
+implementations of the same construction)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "muca.h")
+
+M = pytest.importorskip("paper_1401_4076_amd.muca")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(muca\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["mucaInit", "mucaInitGroups", "mucaSweep", "mucaUpdateWeights", "mucaRun",
+              "mucaIsFlat", "mucaDestroy", "mucaLastError", "mucaReadWalker"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(M.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in M.SIGNATURES, f"binding lacks {name}"
+
+
+def _init_rc(groups, n=None, out=True):
+    arr = (M.muca_group * len(groups))(*[M.muca_group(*g) for g in groups])
+    h = ctypes.c_void_p()
+    return M.lib().mucaInitGroups(ctypes.byref(h) if out else None,
+                                  ctypes.cast(arr, ctypes.c_void_p),
+                                  len(groups) if n is None else n, 1, 0)
+
+
+@pytest.mark.parametrize("g", [
+    (1, 8, 4, 1, 0, 0), (4, 8, 4, 1, 0, 0), (2, 2, 2, 1, 0, 0), (2, 2000, 4, 1, 0, 0),
+    (3, 300, 4, 1, 0, 0), (2, 8, 0, 1, 0, 0), (2, 8, 64, 1, 0, 0), (2, 8, 40, 1, 0, 0),
+    (2, 8, 4, 0, 0, 0), (2, 8, 4, 1, -9, 0), (2, 8, 4, 1, -2, 1), (2, 8, 4, 1, -1, -2),
+])
+def test_invalid_groups_rejected_on_host(g):
+    assert _init_rc([g]) == M.MUCA_EINVAL
+    assert M.lib().mucaLastError().decode() != ""
+
+
+def test_null_arguments_rejected():
+    L = M.lib()
+    assert _init_rc([(2, 8, 4, 1, 0, 0)], out=False) == M.MUCA_EINVAL
+    assert _init_rc([(2, 8, 4, 1, 0, 0)], n=0) == M.MUCA_EINVAL
+    n = ctypes.c_int()
+    assert L.mucaNumGroups(None, ctypes.byref(n)) == M.MUCA_EINVAL
+    assert L.mucaSweep(None, None, 1, None, None) == M.MUCA_EINVAL
+    assert L.mucaUpdateWeights(None, None, None, None, 0, None) == M.MUCA_EINVAL
+    assert L.mucaDestroy(None) == M.MUCA_OK
+    assert L.mucaDefaultWindow(2, 8, 4, None, None) == M.MUCA_EINVAL
+
+
+@pytest.mark.parametrize("d,L,Ns", [
+    (2, 8, range(1, 33)), (2, 32, range(1, 513, 7)), (2, 64, [51, 102, 115, 230, 205, 410]),
+    (2, 48, [115, 230]), (3, 4, range(1, 33)), (3, 16, range(1, 700, 13)),
+    (3, 24, [276, 553, 829, 1382]), (3, 32, [655, 1311, 1966, 3277]), (3, 48, [3318]),
+    (3, 5, range(1, 63)),
+])
+def test_default_window_matches_oracle(d, L, Ns):
+    for N in Ns:
+        assert M.mucaDefaultWindow(d, L, N) == (O.energy_floor(d, L, N), 0), (d, L, N)
