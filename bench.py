@@ -1,0 +1,181 @@
+"""Benchmark of the MUCA iteration on one MI355X.
+
+One step = one iteration of the parallel multicanonical method (paper
+Sec. 2) over the whole batch of walkers: acceptance thresholds from lnW,
+`sweeps` sweeps of every walker (histogram fill and sum, eq. (2)), flatness
+test and the binary64 weight recursion.  The default workload is the batched
+2D lattice gas: 6 groups (L, rho) in {32, 48, 64} x {0.05, 0.10}, 4096
+walkers, 1e4 sweeps per iteration, starting from flat weights; inputs are
+synthetic and resident in device memory when timing starts.
+
+Prints one JSON line: move attempts/s (attempts = sum over walkers of
+sweeps x L^d, accepted or not), the VALU roofline of the sweep kernel and
+the CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops/s
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# One Philox4x32-10 block: 10 rounds of two 32x32->64 products (quarter rate,
+# 4 full-rate equivalents each) and two three-input XORs.
+PHILOX_OPS = 10 * (2 * 4 + 2)
+
+
+def attempts_per_sweep(groups):
+    return sum(g[3] * g[1] ** g[0] for g in groups)
+
+
+def philox_blocks_per_attempt(groups):
+    """Expected Philox blocks per attempt (weighted over walkers): block 0
+    always; block 1 when the first two candidate sites are occupied (~rho^2)."""
+    tot = sum(g[3] * g[1] ** g[0] for g in groups)
+    acc = 0.0
+    for d, L, N, w, *_ in groups:
+        rho = N / L ** d
+        acc += w * L ** d * (1.0 + rho * rho / (1.0 - rho))
+    return acc / tot
+
+
+def cpu_baseline(groups, seed, sample_sweeps):
+    import oracle as O
+    ref = O.RefContext(groups, seed)
+    lnW = np.zeros(ref.total_bins)
+    t0 = time.perf_counter()
+    H = ref.sweep(lnW, sample_sweeps)
+    dt = time.perf_counter() - t0
+    n = attempts_per_sweep(groups) * sample_sweeps
+    assert int(H.sum()) == sum(g[3] for g in groups) * sample_sweeps
+    return {"value": n / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {ref.nwalkers} walkers x {sample_sweeps} sweeps "
+                      f"({n:.3g} attempts, flat weights) in {dt:.1f} s, single thread"}
+
+
+def calibrate_copy(nbytes):
+    """A plain device copy of known size (for scaling HBM byte counters)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched_2d", choices=sorted(W.WORKLOADS))
+    ap.add_argument("--sweeps", type=int, default=None, help="sweeps per iteration")
+    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 lane, 2 wave")
+    ap.add_argument("--cpu-sweeps", type=int, default=None,
+                    help="sweeps of the CPU oracle sample (default: ~10 s of work)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of walkers is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+
+    import torch
+    from paper_1401_4076_amd import muca as M
+
+    wl = W.WORKLOADS[args.workload]
+    groups, seed = wl["groups"], wl["seed"]
+    sweeps = args.sweeps or wl["sweeps"]
+    print(f"bench: workload={args.workload} groups={groups} sweeps={sweeps} "
+          f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    ctx = M.Context(groups, seed)
+    ctx.set_layout(args.layout)
+    dev = torch.device("cuda")
+    lnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device=dev)
+    P = torch.zeros_like(lnW)
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
+    flags = torch.zeros(ctx.ngroups, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def step(timed):
+        if timed:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+        ctx.sweep(lnW, sweeps, H, stream=stream)  # thresholds + sweep kernel
+        if timed:
+            b.record(stream)
+            ev.append((a, b))
+        ctx.is_flat(H, flags, stream=stream)
+        ctx.update_weights(H, lnW, P, M.MUCA_RULE_BERG, stream=stream)
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        print(f"bench: warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        if args.steps > 1:
+            torch.cuda.synchronize()  # progress line per step (steps last seconds)
+            print(f"bench: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.status(stream)
+
+    per_step = attempts_per_sweep(groups) * sweeps
+    dt = t1 - t0
+    value = per_step * args.steps / dt
+    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ops = per_step * philox_blocks_per_attempt(groups) * PHILOX_OPS
+    achieved = ops / (sweep_ms * 1e-3)
+    out = {
+        "metric": "move attempts/s on 1 GPU",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "groups": [list(g) for g in groups],
+                   "walkers": sum(g[3] for g in groups), "sweeps_per_iter": sweeps,
+                   "attempts_per_step": per_step, "rule": "berg", "layout": ctx.layout()},
+        "sweep_kernel_ms": sweep_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS,
+                     "unit": "int32 lane-op/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        cs = args.cpu_sweeps
+        if cs is None:
+            cs = max(1, int(round(1.2e8 / attempts_per_sweep(groups))))
+        print(f"bench: CPU oracle sample, {cs} sweeps of all walkers", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(groups, seed, cs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,9 +59,10 @@ extern "C" {
 #define MUCA_RULE_BERG 0   /* recursive scheme of Sec. 2, read as Berg's error-weighted recursion */
 #define MUCA_RULE_SIMPLE 1 /* W^{i+1}(E) = W^i(E) / H^i(E), Sec. 2 */
 
-#define MUCA_LAYOUT_AUTO 0 /* pick per context by timing (autotuner) */
-#define MUCA_LAYOUT_LANE 1 /* one walker per lane, lattice in LDS or HBM */
-#define MUCA_LAYOUT_WAVE 2 /* one walker per wavefront, speculative batches of attempts */
+#define MUCA_LAYOUT_AUTO 0  /* chosen per context (see mucaAutotune) */
+#define MUCA_LAYOUT_LANE 1  /* one walker per lane, walker state in device memory */
+#define MUCA_LAYOUT_SUB16 2 /* 16 lanes per walker (4 walkers per wavefront) */
+#define MUCA_LAYOUT_SUB64 3 /* 64 lanes (one wavefront) per walker */
 
 typedef struct muca_context* muca_ctx;
 
@@ -108,11 +109,29 @@ int mucaNumWalkers(muca_ctx ctx, int* nwalkers);
 int mucaTotalBins(muca_ctx ctx, int* total_bins);
 int mucaGetWindow(muca_ctx ctx, int group, int32_t* e_lo, int32_t* e_hi, int32_t* bin_offset);
 
-/* Kernel layout used by the sweep (MUCA_LAYOUT_*).  AUTO times the
- * candidates on the first sweep and keeps the fastest.  Results are the same
- * for every layout. */
+/* Kernel layout used by the sweep (MUCA_LAYOUT_*).  Results are the same
+ * for every layout; only the speed differs.  In the cooperative layouts the
+ * walker state sits in LDS for the whole launch when the block's walkers fit
+ * (mucaGetLayout reports the resolved layout; AUTO resolves to SUB16 until
+ * mucaAutotune has run). */
 int mucaSetLayout(muca_ctx ctx, int layout);
 int mucaGetLayout(muca_ctx ctx, int* layout);
+
+/* Largest LDS allocation (bytes per block of 256 lanes) the cooperative
+ * layouts may use, capped by the device limit.  Walker state (occupation
+ * bits and particle sites of the block's walkers) goes to LDS when it fits,
+ * then the group's threshold table when it fits beside it; what does not
+ * fit stays in device memory.  Default 163840; 0 keeps everything in device
+ * memory. */
+int mucaSetLdsLimit(muca_ctx ctx, int64_t bytes);
+
+/* Time every layout on `probe_sweeps` sweeps with weights lnW (device) and
+ * keep the fastest; synchronous.  Walker state is saved before and restored
+ * after the probes, so the call does not change any later result.  chosen
+ * (host, may be NULL) receives the layout, ms (host, may be NULL, 4 doubles)
+ * the probe time per layout index (0 where not run). */
+int mucaAutotune(muca_ctx ctx, const double* lnW, int probe_sweeps, int* chosen, double* ms,
+                 void* stream);
 
 /* Acceptance thresholds from the weights (Sec. 2, min(1, W(E_n)/W(E_o))):
  * for every group, bin b_o and energy change dE in [-2d, 2d],

@@ -29,6 +29,12 @@ struct GroupDesc {
   int64_t pos_off;                // first particle entry of the group's walker 0
 };
 
+// A block of the cooperative sweep: walkers [first, first + count) (global
+// walker indices) of one group.
+struct SweepTask {
+  int32_t group, first, count, pad_;
+};
+
 // ---------------------------------------------------------------- Philox4x32-10
 // Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds of two 32x32->64 products
 // with the Weyl-sequence key schedule.
@@ -88,6 +94,27 @@ __device__ __forceinline__ void neighbours(const GroupDesc& g, uint32_t s, uint3
     nb[4] = (z == (uint32_t)(L - 1)) ? s - slab : s + (uint32_t)g.LL;
     nb[5] = (z == 0) ? s + slab : s - (uint32_t)g.LL;
   }
+}
+
+// Neighbour of site s in direction dir: axis dir/2, +1 for even dir, -1 for odd.
+__device__ __forceinline__ uint32_t neighbour1(const GroupDesc& g, uint32_t s, int dir) {
+  const uint32_t L = (uint32_t)g.L;
+  const uint32_t q = div_L(s, g.L, g.invL);
+  const int axis = dir >> 1;
+  const bool up = (dir & 1) == 0;
+  uint32_t c, stride;
+  if (axis == 0) {
+    c = s - q * L;
+    stride = 1;
+  } else if (axis == 1) {
+    c = (g.d == 2) ? q : q - div_L(q, g.L, g.invL) * L;
+    stride = L;
+  } else {
+    c = div_L(q, g.L, g.invL);
+    stride = (uint32_t)g.LL;
+  }
+  if (up) return (c == L - 1) ? s - (L - 1) * stride : s + stride;
+  return (c == 0) ? s + (L - 1) * stride : s - stride;
 }
 
 // ---------------------------------------------------------------- exp / log

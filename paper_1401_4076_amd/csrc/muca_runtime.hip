@@ -17,6 +17,7 @@
 #include "muca_kernels.h"
 
 using muca::GroupDesc;
+using muca::SweepTask;
 
 namespace {
 
@@ -120,8 +121,18 @@ struct muca_context {
   int32_t* d_iters = nullptr;
   int32_t* d_counter = nullptr;  // [0] iteration index, [1] groups still active
   int32_t* h_pinned = nullptr;   // host-pinned readback of the counters
-  int layout = MUCA_LAYOUT_AUTO;
+  int layout = MUCA_LAYOUT_AUTO;  // requested
+  int tuned = 0;                  // layout picked by mucaAutotune (0 = none yet)
   hipStream_t last_stream = nullptr;
+  // cooperative layouts: one task table per lanes-per-walker choice
+  struct Coop {
+    SweepTask* d_tasks = nullptr;
+    int ntasks = 0;
+    size_t need = 0;       // LDS bytes for the walker state of the largest block
+  } coop[2];               // [0]: 16 lanes per walker, [1]: 64 lanes per walker
+  size_t tbl_bytes = 0;    // largest threshold table of one group
+  size_t lds_limit = 160 * 1024;  // LDS a cooperative block may use
+  size_t lds_device = 64 * 1024;  // device maximum per block
 
   ~muca_context() {
     (void)hipFree(d_groups);
@@ -138,6 +149,7 @@ struct muca_context {
     (void)hipFree(d_flat);
     (void)hipFree(d_iters);
     (void)hipFree(d_counter);
+    for (auto& q : coop) (void)hipFree(q.d_tasks);
     if (h_pinned) (void)hipHostFree(h_pinned);
   }
 };
@@ -159,20 +171,101 @@ int enqueue_thresholds(muca_ctx c, const double* lnW, hipStream_t s) {
   return MUCA_OK;
 }
 
-int enqueue_sweep(muca_ctx c, const double* lnW, int sweeps, int32_t* H, const int32_t* active,
-                  hipStream_t s) {
-  int rc = enqueue_thresholds(c, lnW, s);
-  if (rc) return rc;
+int resolved_layout(muca_ctx c) {
+  if (c->layout != MUCA_LAYOUT_AUTO) return c->layout;
+  return c->tuned ? c->tuned : MUCA_LAYOUT_SUB16;
+}
+
+// Blocks of 256 threads hold 256/G walkers of one group; the blocks of the
+// groups are interleaved so that every CU receives a mix of lattice sizes.
+int build_coop(muca_ctx c, int which) {
+  auto& q = c->coop[which];
+  if (q.d_tasks) return MUCA_OK;
+  const int G = which == 0 ? 16 : 64;
+  const int wpb = 256 / G;
+  std::vector<std::vector<SweepTask>> per(c->ngroups);
+  size_t need = 0;
+  for (int i = 0; i < c->ngroups; ++i) {
+    const GroupDesc& g = c->g[i];
+    for (int f = 0; f < g.walkers; f += wpb)
+      per[i].push_back(SweepTask{i, g.first_walker + f, std::min(wpb, g.walkers - f), 0});
+    need = std::max(need, (size_t)wpb * (size_t)(g.words + 2 * g.N) * sizeof(uint32_t));
+  }
+  std::vector<SweepTask> tasks;
+  for (size_t r = 0;; ++r) {
+    bool any = false;
+    for (auto& v : per)
+      if (r < v.size()) {
+        tasks.push_back(v[r]);
+        any = true;
+      }
+    if (!any) break;
+  }
+  q.ntasks = (int)tasks.size();
+  q.need = need;
+  c->tbl_bytes = 0;
+  for (const auto& g : c->g)
+    c->tbl_bytes = std::max(c->tbl_bytes, (size_t)g.nbins * (size_t)g.nd * sizeof(uint32_t));
+  if (int r = dev_alloc(&q.d_tasks, tasks.size())) return r;
+  HIP_TRY(hipMemcpy(q.d_tasks, tasks.data(), sizeof(SweepTask) * tasks.size(),
+                    hipMemcpyHostToDevice));
+  return MUCA_OK;
+}
+
+template <int G>
+int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* active,
+                hipStream_t s) {
+  if (int r = build_coop(c, which)) return r;
+  const auto& q = c->coop[which];
+  const size_t cap = std::min(c->lds_limit, c->lds_device);
+  const bool state_lds = q.need <= cap;
+  const size_t state = state_lds ? q.need : 0;
+  const bool tbl_lds = c->lds_limit > 0 && state + c->tbl_bytes <= cap;
+  const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
+  const int tbl_words = tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0;
+  auto kern = state_lds ? muca::k_sweep_sub<G, true> : muca::k_sweep_sub<G, false>;
+  if (dyn > 64 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)dyn));
+  hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
+                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active, sweeps,
+                     c->first_id, c->seed32, tbl_words);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
+int enqueue_sweep_kernel(muca_ctx c, int layout, int sweeps, int32_t* H, const int32_t* active,
+                         hipStream_t s) {
+  switch (layout) {
+    case MUCA_LAYOUT_LANE:
+      hipLaunchKernelGGL(muca::k_sweep_lane, dim3((unsigned)((c->nwalkers + 63) / 64)), dim3(64),
+                         0, s, c->d_groups, c->d_wgroup, c->d_bits, c->d_pos, c->d_E, c->d_T,
+                         c->d_thr, H, active, c->nwalkers, sweeps, c->first_id, c->seed32);
+      LAUNCH_CHECK();
+      return MUCA_OK;
+    case MUCA_LAYOUT_SUB16:
+      return launch_coop<16>(c, 0, sweeps, H, active, s);
+    case MUCA_LAYOUT_SUB64:
+      return launch_coop<64>(c, 1, sweeps, H, active, s);
+    default:
+      return fail(MUCA_EINVAL, "unknown layout %d", layout);
+  }
+}
+
+int enqueue_zero_hist(muca_ctx c, int32_t* H, const int32_t* active, hipStream_t s) {
   int maxb = 0;
   for (const auto& q : c->g) maxb = std::max(maxb, q.nbins);
   hipLaunchKernelGGL(muca::k_zero_hist, dim3((unsigned)((maxb + 255) / 256), (unsigned)c->ngroups),
                      dim3(256), 0, s, c->d_groups, active, H);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(muca::k_sweep_lane, dim3((unsigned)((c->nwalkers + 63) / 64)), dim3(64), 0, s,
-                     c->d_groups, c->d_wgroup, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H,
-                     active, c->nwalkers, sweeps, c->first_id, c->seed32);
-  LAUNCH_CHECK();
   return MUCA_OK;
+}
+
+int enqueue_sweep(muca_ctx c, const double* lnW, int sweeps, int32_t* H, const int32_t* active,
+                  hipStream_t s) {
+  if (int rc = enqueue_thresholds(c, lnW, s)) return rc;
+  if (int rc = enqueue_zero_hist(c, H, active, s)) return rc;
+  return enqueue_sweep_kernel(c, resolved_layout(c), sweeps, H, active, s);
 }
 
 int check_sweeps(muca_ctx c, int sweeps) {
@@ -256,6 +349,11 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
   c->total_words = words;
   c->total_pos = pos;
   HIP_TRY_DEL(hipGetDevice(&c->device));
+  {
+    int v = 0;
+    HIP_TRY_DEL(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    c->lds_device = (size_t)v;
+  }
 
   std::vector<int32_t> wg((size_t)walkers);
   for (int i = 0; i < ngroups; ++i)
@@ -366,7 +464,7 @@ int mucaGetWindow(muca_ctx c, int group, int32_t* e_lo, int32_t* e_hi, int32_t* 
 
 int mucaSetLayout(muca_ctx c, int layout) {
   if (int r = check_ctx(c)) return r;
-  if (layout < MUCA_LAYOUT_AUTO || layout > MUCA_LAYOUT_WAVE)
+  if (layout < MUCA_LAYOUT_AUTO || layout > MUCA_LAYOUT_SUB64)
     return fail(MUCA_EINVAL, "unknown layout %d", layout);
   c->layout = layout;
   return MUCA_OK;
@@ -375,7 +473,86 @@ int mucaSetLayout(muca_ctx c, int layout) {
 int mucaGetLayout(muca_ctx c, int* layout) {
   if (int r = check_ctx(c)) return r;
   if (!layout) return fail(MUCA_EINVAL, "null output");
-  *layout = c->layout;
+  *layout = resolved_layout(c);
+  return MUCA_OK;
+}
+
+int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, double* ms,
+                 void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW) return fail(MUCA_EINVAL, "lnW is NULL");
+  if (int r = check_sweeps(c, probe_sweeps)) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  // save walker state
+  uint32_t *b0 = nullptr, *p0 = nullptr;
+  int32_t *e0 = nullptr, *h = nullptr;
+  uint64_t* t0 = nullptr;
+  int rc = MUCA_OK;
+  double best = 1e300;
+  int pick = MUCA_LAYOUT_SUB16;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  auto save = [&](bool back) -> int {
+    const auto k = hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(back ? c->d_bits : b0, back ? b0 : c->d_bits,
+                           sizeof(uint32_t) * (size_t)c->total_words, k, s));
+    HIP_TRY(hipMemcpyAsync(back ? c->d_pos : p0, back ? p0 : c->d_pos,
+                           sizeof(uint32_t) * (size_t)c->total_pos, k, s));
+    HIP_TRY(hipMemcpyAsync(back ? c->d_E : e0, back ? e0 : c->d_E,
+                           sizeof(int32_t) * (size_t)c->nwalkers, k, s));
+    HIP_TRY(hipMemcpyAsync(back ? c->d_T : t0, back ? t0 : c->d_T,
+                           sizeof(uint64_t) * (size_t)c->nwalkers, k, s));
+    return MUCA_OK;
+  };
+  auto body = [&]() -> int {
+    int r;
+    if ((r = dev_alloc(&b0, (size_t)c->total_words))) return r;
+    if ((r = dev_alloc(&p0, (size_t)c->total_pos))) return r;
+    if ((r = dev_alloc(&e0, (size_t)c->nwalkers))) return r;
+    if ((r = dev_alloc(&t0, (size_t)c->nwalkers))) return r;
+    if ((r = dev_alloc(&h, (size_t)c->total_bins))) return r;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    if ((r = save(false))) return r;
+    if ((r = enqueue_thresholds(c, lnW, s))) return r;
+    for (int lay = MUCA_LAYOUT_LANE; lay <= MUCA_LAYOUT_SUB64; ++lay) {
+      if ((r = enqueue_zero_hist(c, h, c->d_ones, s))) return r;
+      HIP_TRY(hipEventRecord(ev0, s));
+      if ((r = enqueue_sweep_kernel(c, lay, probe_sweeps, h, c->d_ones, s))) return r;
+      HIP_TRY(hipEventRecord(ev1, s));
+      HIP_TRY(hipEventSynchronize(ev1));
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ev0, ev1));
+      if (ms) ms[lay] = t;
+      if (t < best) {
+        best = t;
+        pick = lay;
+      }
+      if ((r = save(true))) return r;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return MUCA_OK;
+  };
+  if (ms)
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+  rc = body();
+  (void)hipFree(b0);
+  (void)hipFree(p0);
+  (void)hipFree(e0);
+  (void)hipFree(t0);
+  (void)hipFree(h);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (rc) return rc;
+  c->tuned = pick;
+  if (chosen) *chosen = pick;
+  return MUCA_OK;
+}
+
+int mucaSetLdsLimit(muca_ctx c, int64_t bytes) {
+  if (int r = check_ctx(c)) return r;
+  if (bytes < 0 || bytes > 160 * 1024) return fail(MUCA_EINVAL, "LDS limit must be in [0, 163840]");
+  c->lds_limit = (size_t)bytes;
   return MUCA_OK;
 }
 

@@ -1,0 +1,384 @@
+// muca_sweep_sub.hip -- equilibrium sweep with G lanes cooperating on one
+// walker (paper Sec. 2: fixed weights, Metropolis acceptance
+// min(1, W(E_n)/W(E_o)); Sec. 4: a sweep is L^d attempts).
+//
+// A Markov chain is sequential, so a walker's attempts are decided one after
+// the other.  The G lanes of a walker share the work around each decision:
+//  * batch phase (lane-parallel): lane l takes attempt t + l of the next G:
+//    its Philox block, the particle k, the candidate sites c2, c3 with their
+//    coordinates, and s_o = pos[k] read from the walker state;
+//  * per attempt: the attempt's values are broadcast (DPP row broadcast for
+//    16 lanes, readlane for 64), and one lane-parallel gather reads the
+//    occupation of the 2d neighbours of s_o, of c2, c3 and of the 2d
+//    neighbours of c2; each lane computes its site from per-lane constants
+//    (axis, direction, periodic wrap), without branches;
+//  * the threshold row T[E][.] stays in lanes 0..4d; every lane tests the
+//    attempt's uniform u against its entry and a ballot picks the entry of
+//    the attempt's dE;
+//  * an accepted move is written to the walker state and patched into the
+//    prefetched s_o of the later attempts of the batch that chose the same
+//    particle, so the prefetch always equals pos[k] at decision time.
+// Random-number consumption, candidate order and decisions are those of the
+// one-walker-per-lane kernel, so all layouts give identical results.
+//
+// kLds: walker state (occupation bits, particle sites and their packed
+// coordinates) lives in LDS for the whole launch; otherwise occupation bits
+// and sites stay in device memory (workgroup-coherent accesses) and the
+// coordinates of s_o are recomputed in the batch phase.
+#include "muca_kernels.h"
+
+#pragma clang fp contract(off)
+
+namespace muca {
+
+namespace {
+
+constexpr uint32_t kCoordBits = 10;  // packed coordinates x | y << 10 | z << 20
+constexpr uint32_t kCoordMask = (1u << kCoordBits) - 1u;
+
+__device__ __forceinline__ uint32_t pack_coords(const GroupDesc& g, uint32_t s) {
+  const uint32_t q = div_L(s, g.L, g.invL);
+  const uint32_t x = s - q * (uint32_t)g.L;
+  if (g.d == 2) return x | (q << kCoordBits);
+  const uint32_t z = div_L(q, g.L, g.invL);
+  const uint32_t y = q - z * (uint32_t)g.L;
+  return x | (y << kCoordBits) | (z << (2 * kCoordBits));
+}
+
+template <bool kLds>
+__device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+  if constexpr (kLds) return *p;
+  else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <bool kLds>
+__device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
+  if constexpr (kLds) *p = v;
+  else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <bool kLds>
+__device__ __forceinline__ void flip(uint32_t* bits, uint32_t so, uint32_t sn) {
+  if constexpr (kLds) {
+    atomicAnd(&bits[so >> 5], ~(1u << (so & 31u)));
+    atomicOr(&bits[sn >> 5], 1u << (sn & 31u));
+  } else {
+    __hip_atomic_fetch_and(&bits[so >> 5], ~(1u << (so & 31u)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_or(&bits[sn >> 5], 1u << (sn & 31u), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Per-lane constants of one neighbour role: coordinate field, edge value,
+// step and wrapped step along the lane's axis and direction.
+struct NbrRole {
+  uint32_t shift, edge;
+  int32_t step, wrap;
+};
+
+__device__ __forceinline__ NbrRole make_role(const GroupDesc& g, int dir) {
+  NbrRole r{0u, 0xFFFFFFFFu, 0, 0};  // dir < 0: the site itself
+  if (dir < 0) return r;
+  const int axis = dir >> 1;
+  const int32_t stride = axis == 0 ? 1 : (axis == 1 ? g.L : g.LL);
+  r.shift = kCoordBits * (uint32_t)axis;
+  if ((dir & 1) == 0) {
+    r.edge = (uint32_t)(g.L - 1);
+    r.step = stride;
+    r.wrap = -(g.L - 1) * stride;
+  } else {
+    r.edge = 0u;
+    r.step = -stride;
+    r.wrap = (g.L - 1) * stride;
+  }
+  return r;
+}
+
+__device__ __forceinline__ uint32_t role_site(const NbrRole& r, uint32_t lin, uint32_t xyz) {
+  const uint32_t c = (xyz >> r.shift) & kCoordMask;
+  return lin + (uint32_t)((c == r.edge) ? r.wrap : r.step);
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t sub_mask(uint64_t ballot, int base) {
+  if constexpr (G == 64) return (uint32_t)ballot;
+  else return (uint32_t)(ballot >> base) & ((1u << G) - 1u);
+}
+
+// Broadcast lane A (compile-time) of each 16-lane row, or lane a of the wave.
+template <int A>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + A, 0xF, 0xF, false);
+}
+
+// Walker state and per-lane constants of one cooperative walker.
+template <int G, bool kLds>
+struct Walker {
+  const GroupDesc* g;
+  uint32_t* bits;
+  uint32_t* plin;
+  uint32_t* pxyz;  // LDS mode only
+  const uint32_t* th;  // threshold table in device memory
+  const uint32_t* tl;  // the same table in LDS, or nullptr
+  int32_t* hist;
+  int ls, base, d2, nd;
+  uint32_t V, N, key0, seed32, in_sweep;
+  int32_t E;
+  uint64_t t;
+  uint32_t Trow;
+  // lane roles of the main gather: [0,2d) nbr(s_o), 2d: c2, 2d+1: c3,
+  // [2d+2, 4d+2) nbr(c2)
+  NbrRole role;
+  bool role_on, role_so, role_c3;
+  NbrRole role2;  // lanes [0, 2d): nbr of s_n in the second gather
+  // batch values of lane ls (attempt t + ls)
+  uint32_t b_k, b_u, b_c2, b_c2x, b_c3, b_c3x, b_so, b_sox;
+};
+
+template <int G, bool kLds>
+__device__ __forceinline__ uint32_t trow(const Walker<G, kLds>& W, int i) {
+  return W.tl ? W.tl[i] : W.th[i];
+}
+
+template <int G, bool kLds>
+__device__ __forceinline__ void batch_phase(Walker<G, kLds>& W) {
+  const GroupDesc& g = *W.g;
+  const uint64_t tl = W.t + (uint64_t)W.ls;
+  const U4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), 0u, 0u, W.key0, W.seed32);
+  W.b_k = draw(r.x, W.N);
+  W.b_u = r.y;
+  W.b_c2 = draw(r.z, W.V);
+  W.b_c3 = draw(r.w, W.V);
+  W.b_c2x = pack_coords(g, W.b_c2);
+  W.b_c3x = pack_coords(g, W.b_c3);
+  W.b_so = ld<kLds>(&W.plin[W.b_k]);
+  if constexpr (kLds) W.b_sox = W.pxyz[W.b_k];
+  else W.b_sox = pack_coords(g, W.b_so);
+}
+
+// One attempt with broadcast values; returns nothing, updates W.
+template <int G, bool kLds>
+__device__ __forceinline__ void attempt(Walker<G, kLds>& W, uint32_t k, uint32_t u, uint32_t c2,
+                                        uint32_t c2x, uint32_t c3, uint32_t c3x, uint32_t so,
+                                        uint32_t sox, uint64_t ta) {
+  const GroupDesc& g = *W.g;
+  const int d2 = W.d2;
+  const uint32_t dmask = (1u << d2) - 1u;
+  // main gather
+  const uint32_t blin = W.role_so ? so : (W.role_c3 ? c3 : c2);
+  const uint32_t bxyz = W.role_so ? sox : (W.role_c3 ? c3x : c2x);
+  const uint32_t site = role_site(W.role, blin, bxyz);
+  uint32_t v = 0;
+  if (W.role_on) v = ld<kLds>(&W.bits[site >> 5]);
+  const bool occ = W.role_on && ((v >> (site & 31u)) & 1u);
+  const bool isso = W.role_on && (site == so);
+  const uint32_t m = sub_mask<G>(__ballot(occ), W.base);
+  const uint32_t mx = sub_mask<G>(__ballot(isso), W.base);
+  const int ko = __popc(m & dmask);
+  uint32_t sn, snx;
+  int kn;
+  if (!((m >> d2) & 1u)) {
+    sn = c2;
+    snx = c2x;
+    kn = __popc((m >> (d2 + 2)) & ~(mx >> (d2 + 2)) & dmask);
+  } else {
+    if (!((m >> (d2 + 1)) & 1u)) {
+      sn = c3;
+      snx = c3x;
+    } else {
+      // both candidates occupied: words 0..3 of blocks 1, 2, ... in order
+      uint32_t blk = 0;
+      for (;;) {
+        blk += 1;
+        const U4 q = philox((uint32_t)ta, (uint32_t)(ta >> 32), blk, 0u, W.key0, W.seed32);
+        const int l4 = W.ls & 3;
+        const uint32_t word = (l4 == 0) ? q.x : (l4 == 1) ? q.y : (l4 == 2) ? q.z : q.w;
+        const uint32_t cand = draw(word, W.V);
+        uint32_t vv = 0;
+        if (W.ls < 4) vv = ld<kLds>(&W.bits[cand >> 5]);
+        const bool fr = (W.ls < 4) && !((vv >> (cand & 31u)) & 1u);
+        const uint32_t fm = sub_mask<G>(__ballot(fr), W.base) & 0xFu;
+        if (fm) {
+          const int first = __ffs(fm) - 1;
+          const uint32_t words[4] = {q.x, q.y, q.z, q.w};
+          uint32_t pick = words[0];
+          for (int i = 1; i < 4; ++i)
+            if (i == first) pick = words[i];
+          sn = draw(pick, W.V);
+          snx = pack_coords(g, sn);
+          break;
+        }
+      }
+    }
+    // second gather: neighbours of s_n, not counting s_o
+    const uint32_t s3 = role_site(W.role2, sn, snx);
+    uint32_t v3 = 0;
+    const bool on3 = W.ls < d2;
+    if (on3) v3 = ld<kLds>(&W.bits[s3 >> 5]);
+    const bool occ3 = on3 && ((v3 >> (s3 & 31u)) & 1u) && (s3 != so);
+    kn = __popc(sub_mask<G>(__ballot(occ3), W.base));
+  }
+  const int dE = ko - kn;
+  // every lane of the threshold row tests u; the entry of dE decides
+  const bool ok = (W.ls < W.nd) && accepts(W.Trow, u);
+  const uint32_t am = sub_mask<G>(__ballot(ok), W.base);
+  if ((am >> (dE + d2)) & 1u) {
+    if (W.ls == 0) {
+      st<kLds>(&W.plin[k], sn);
+      if constexpr (kLds) W.pxyz[k] = snx;
+      flip<kLds>(W.bits, so, sn);
+    }
+    if constexpr (!kLds) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (W.b_k == k) {  // later attempts of this batch that chose the same particle
+      W.b_so = sn;
+      W.b_sox = snx;
+    }
+    W.E += dE;
+    if (dE != 0 && W.ls < W.nd) W.Trow = trow(W, (W.E - g.e_lo) * W.nd + W.ls);
+  }
+  if (++W.in_sweep == W.V) {
+    W.in_sweep = 0;
+    if (W.ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+  }
+}
+
+template <int A, int G, bool kLds>
+__device__ __forceinline__ void unrolled16(Walker<G, kLds>& W, int nb) {
+  if constexpr (A < 16) {
+    if (A < nb) {
+      attempt<G, kLds>(W, row_bcast<A>(W.b_k), row_bcast<A>(W.b_u), row_bcast<A>(W.b_c2),
+                       row_bcast<A>(W.b_c2x), row_bcast<A>(W.b_c3), row_bcast<A>(W.b_c3x),
+                       row_bcast<A>(W.b_so), row_bcast<A>(W.b_sox), W.t + (uint64_t)A);
+      unrolled16<A + 1, G, kLds>(W, nb);
+    }
+  }
+}
+
+}  // namespace
+
+template <int G, bool kLds>
+__global__ void __launch_bounds__(256) k_sweep_sub(
+    const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
+    uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
+    uint64_t* __restrict__ gT, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
+    const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
+    int tbl_words) {
+  static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
+  extern __shared__ uint32_t smem[];  // [threshold table (tbl_words)] [walker slots]
+  const SweepTask task = tasks[blockIdx.x];
+  if (active && !active[task.group]) return;  // uniform per block
+  const GroupDesc g = groups[task.group];
+  Walker<G, kLds> W;
+  W.g = &g;
+  W.ls = threadIdx.x & (G - 1);
+  W.base = (threadIdx.x & 63) & ~(G - 1);
+  const int slot = threadIdx.x / G;
+  const bool has = slot < task.count;
+  const int w = task.first + slot;
+  const int64_t j = w - g.first_walker;
+  W.d2 = 2 * g.d;
+  W.nd = g.nd;
+  W.V = (uint32_t)g.V;
+  W.N = (uint32_t)g.N;
+  uint32_t* sb = gbits + g.bits_off + j * g.words;
+  uint32_t* sp = gpos + g.pos_off + j * g.N;
+  // the group's threshold table goes to LDS when the launch reserved room
+  const bool tbl_lds = tbl_words > 0;
+  if (tbl_lds) {
+    const uint32_t* src = thr + g.thr_off;
+    const int n = g.nbins * g.nd;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = src[i];
+  }
+  if constexpr (kLds) {
+    W.bits = smem + (size_t)tbl_words + (size_t)slot * (size_t)(g.words + 2 * g.N);
+    W.plin = W.bits + g.words;
+    W.pxyz = W.plin + g.N;
+    if (has) {
+      for (int i = W.ls; i < g.words; i += G) W.bits[i] = sb[i];
+      for (int i = W.ls; i < g.N; i += G) {
+        const uint32_t s = sp[i];
+        W.plin[i] = s;
+        W.pxyz[i] = pack_coords(g, s);
+      }
+    }
+  } else {
+    W.bits = sb;
+    W.plin = sp;
+    W.pxyz = nullptr;
+  }
+  __syncthreads();
+
+  if (has) {
+    const int d2 = W.d2;
+    const int ls = W.ls;
+    W.role_on = ls < 2 * d2 + 2;
+    W.role_so = ls < d2;
+    W.role_c3 = ls == d2 + 1;
+    int dir = -1;
+    if (ls < d2) dir = ls;
+    else if (ls >= d2 + 2 && ls < 2 * d2 + 2) dir = ls - d2 - 2;
+    W.role = make_role(g, dir);
+    W.role2 = make_role(g, ls < d2 ? ls : -1);
+    W.th = thr + g.thr_off;
+    W.tl = tbl_lds ? smem : nullptr;
+    W.hist = H + g.bin_off;
+    W.key0 = first_id + (uint32_t)w;
+    W.seed32 = seed32;
+    W.E = gE[w];
+    W.t = gT[w];
+    W.Trow = (ls < W.nd) ? trow(W, (W.E - g.e_lo) * W.nd + ls) : 0u;
+    W.in_sweep = 0;
+    const int64_t total = (int64_t)sweeps * (int64_t)W.V;
+    for (int64_t done = 0; done < total; done += G) {
+      const int nb = (int)((total - done) < G ? (total - done) : G);
+      batch_phase<G, kLds>(W);
+      if constexpr (G == 16) {
+        unrolled16<0, G, kLds>(W, nb);
+      } else {
+        for (int a = 0; a < nb; ++a) {
+          attempt<G, kLds>(W, __builtin_amdgcn_readlane(W.b_k, a),
+                           __builtin_amdgcn_readlane(W.b_u, a),
+                           __builtin_amdgcn_readlane(W.b_c2, a),
+                           __builtin_amdgcn_readlane(W.b_c2x, a),
+                           __builtin_amdgcn_readlane(W.b_c3, a),
+                           __builtin_amdgcn_readlane(W.b_c3x, a),
+                           __builtin_amdgcn_readlane(W.b_so, a),
+                           __builtin_amdgcn_readlane(W.b_sox, a), W.t + (uint64_t)a);
+        }
+      }
+      W.t += (uint64_t)nb;
+    }
+    if (ls == 0) {
+      gE[w] = W.E;
+      gT[w] = W.t;
+    }
+  }
+
+  if constexpr (kLds) {
+    __syncthreads();
+    if (has) {
+      for (int i = W.ls; i < g.words; i += G) sb[i] = W.bits[i];
+      for (int i = W.ls; i < g.N; i += G) sp[i] = W.plin[i];
+    }
+  }
+}
+
+template __global__ void k_sweep_sub<16, true>(const GroupDesc*, const SweepTask*, uint32_t*,
+                                                uint32_t*, int32_t*, uint64_t*,
+                                                const uint32_t*, int32_t*, const int32_t*, int,
+                                                uint32_t, uint32_t, int);
+template __global__ void k_sweep_sub<16, false>(const GroupDesc*, const SweepTask*, uint32_t*,
+                                                uint32_t*, int32_t*, uint64_t*,
+                                                const uint32_t*, int32_t*, const int32_t*, int,
+                                                uint32_t, uint32_t, int);
+template __global__ void k_sweep_sub<64, true>(const GroupDesc*, const SweepTask*, uint32_t*,
+                                                uint32_t*, int32_t*, uint64_t*,
+                                                const uint32_t*, int32_t*, const int32_t*, int,
+                                                uint32_t, uint32_t, int);
+template __global__ void k_sweep_sub<64, false>(const GroupDesc*, const SweepTask*, uint32_t*,
+                                                uint32_t*, int32_t*, uint64_t*,
+                                                const uint32_t*, int32_t*, const int32_t*, int,
+                                                uint32_t, uint32_t, int);
+
+}  // namespace muca

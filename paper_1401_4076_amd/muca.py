@@ -26,7 +26,9 @@ MUCA_RULE_BERG = 0
 MUCA_RULE_SIMPLE = 1
 MUCA_LAYOUT_AUTO = 0
 MUCA_LAYOUT_LANE = 1
-MUCA_LAYOUT_WAVE = 2
+MUCA_LAYOUT_SUB16 = 2
+MUCA_LAYOUT_SUB64 = 3
+LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64)
 
 # C ABI: name -> (restype, argtypes)
 _P = ctypes.POINTER
@@ -47,6 +49,9 @@ SIGNATURES = {
     "mucaGetWindow": (ctypes.c_int, [_vp, ctypes.c_int, _P(_i32), _P(_i32), _P(_i32)]),
     "mucaSetLayout": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaGetLayout": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
+    "mucaAutotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _P(ctypes.c_int),
+                                    _P(ctypes.c_double), _vp]),
+    "mucaSetLdsLimit": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "mucaThresholdEntries": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
     "mucaBuildThresholds": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaSweep": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
@@ -161,6 +166,17 @@ class Context:
 
     def layout(self):
         return self._int(lib().mucaGetLayout)
+
+    def set_lds_limit(self, nbytes):
+        _check(lib().mucaSetLdsLimit(self._h, int(nbytes)))
+
+    def autotune(self, lnW, probe_sweeps=1, stream=None):
+        """Returns (chosen layout, [ms per layout index 0..3])."""
+        ch = ctypes.c_int()
+        ms = (ctypes.c_double * 4)()
+        _check(lib().mucaAutotune(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
+                                  int(probe_sweeps), ctypes.byref(ch), ms, _stream(stream)))
+        return ch.value, list(ms)
 
     def build_thresholds(self, lnW, out=None, stream=None):
         p = _dev(lnW, torch.float64, self.total_bins, "lnW")

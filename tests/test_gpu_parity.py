@@ -143,15 +143,32 @@ def test_flatness_matches_oracle():
         assert np.array_equal(flags.cpu().numpy(), ref.flat(H)), trial
 
 
+# (layout, LDS limit): every kernel variant, with walker state in LDS and in
+# device memory
+VARIANTS = [(M.MUCA_LAYOUT_LANE, 65536), (M.MUCA_LAYOUT_SUB16, 65536), (M.MUCA_LAYOUT_SUB16, 0),
+            (M.MUCA_LAYOUT_SUB64, 65536), (M.MUCA_LAYOUT_SUB64, 0)]
+VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm"]
+
+
+def make_ctx(groups, seed, variant=None, first_id=0):
+    ctx = M.Context(groups, seed, first_id)
+    if variant is not None:
+        ctx.set_layout(variant[0])
+        ctx.set_lds_limit(variant[1])
+    return ctx
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
 @pytest.mark.parametrize("groups,sweeps", [
     (MIXED, 7),
     ([(2, 8, 16, 64)], 30),
     ([(3, 3, 5, 10), (3, 16, 205, 3)], 3),
     ([(2, 9, 20, 5, -30, -2)], 11),
+    ([(2, 4, 8, 17, -12, 0), (3, 4, 30, 6, -80, 0)], 9),   # dense: many rejected candidates
 ])
-def test_sweep_matches_oracle(groups, sweeps):
-    say("sweep", groups, sweeps)
-    ctx = M.Context(groups, seed=2)
+def test_sweep_matches_oracle(groups, sweeps, variant):
+    say("sweep", groups, sweeps, variant)
+    ctx = make_ctx(groups, 2, variant)
     ref = O.RefContext(groups, seed=2)
     lnW = W.random_lnW(ctx.total_bins, seed=9, scale=1.5)
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
@@ -182,9 +199,10 @@ def test_sweep_active_mask():
 
 
 def _run_both(groups, seed, sweeps, iters, rule=0, stop_on_flat=False, lnW0=None,
-              check_walkers=True):
-    say("run", groups, "sweeps", sweeps, "iters", iters, "rule", rule, "flat", stop_on_flat)
-    ctx = M.Context(groups, seed)
+              check_walkers=True, variant=None):
+    say("run", groups, "sweeps", sweeps, "iters", iters, "rule", rule, "flat", stop_on_flat,
+        "variant", variant)
+    ctx = make_ctx(groups, seed, variant)
     ref = O.RefContext(groups, seed)
     lnW = np.zeros(ctx.total_bins) if lnW0 is None else np.array(lnW0, dtype=np.float64)
     P = np.full(ctx.total_bins, 123.0)  # mucaRun zeroes P itself
@@ -204,30 +222,34 @@ def _run_both(groups, seed, sweeps, iters, rule=0, stop_on_flat=False, lnW0=None
     return rc, it, fl
 
 
-def test_run_plain_2d_full_schedule():
+@pytest.mark.parametrize("variant", [VARIANTS[0], VARIANTS[1]], ids=VARIANT_IDS[:2])
+def test_run_plain_2d_full_schedule(variant):
     # 2D L=8, N=16, 64 walkers, 10 iterations x 1e4 sweeps from lnW = 0
     wl = W.WORKLOADS["plain_2d"]
-    _run_both(wl["groups"], wl["seed"], wl["sweeps"], wl["iters"])
+    _run_both(wl["groups"], wl["seed"], wl["sweeps"], wl["iters"], variant=variant)
 
 
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
 @pytest.mark.parametrize("name,walkers,sweeps,iters", [
     ("batched_2d", 8, 40, 3),
     ("cubic_3d", 16, 20, 3),
     ("batched_3d", 2, 2, 2),
     ("large_3d", 2, 1, 2),
 ])
-def test_run_reduced_workloads(name, walkers, sweeps, iters):
+def test_run_reduced_workloads(name, walkers, sweeps, iters, variant):
     wl = W.scaled(name, walkers_per_group=walkers, sweeps=sweeps)
-    _run_both(wl["groups"], wl["seed"], wl["sweeps"], iters, stop_on_flat=wl["stop_on_flat"])
+    _run_both(wl["groups"], wl["seed"], wl["sweeps"], iters, stop_on_flat=wl["stop_on_flat"],
+              variant=variant)
 
 
 FLAT_GROUPS = [(2, 4, 5, 64, -5, 0), (2, 6, 10, 16, 0, 0), (3, 4, 4, 16, -4, 0),
                (2, 8, 12, 16, 0, 0), (2, 7, 9, 8, 0, 0)]
 
 
-def test_run_until_flat_per_group():
+@pytest.mark.parametrize("variant", VARIANTS[:2], ids=VARIANT_IDS[:2])
+def test_run_until_flat_per_group(variant):
     # the groups go flat at different iterations (2, 4, 3, 7, 10 for this seed)
-    rc, it, fl = _run_both(FLAT_GROUPS, 5, 50, 80, rule=0, stop_on_flat=True)
+    rc, it, fl = _run_both(FLAT_GROUPS, 5, 50, 80, rule=0, stop_on_flat=True, variant=variant)
     assert rc == 0 and all(fl) and len(set(it)) >= 4
 
 
@@ -262,16 +284,17 @@ def test_edge_single_particle_and_small_lattices():
     assert_walkers_equal(ctx, ref, range(ctx.nwalkers))
 
 
+@pytest.mark.parametrize("variant", [None] + VARIANTS[1:], ids=["auto"] + VARIANT_IDS[1:])
 @pytest.mark.parametrize("name,sample", [("batched_2d", 12), ("large_3d", 4),
                                          ("batched_3d", 8), ("cubic_3d", 6)])
-def test_full_size_sampled_walkers(name, sample):
+def test_full_size_sampled_walkers(name, sample, variant):
     """Full walker populations: every walker sweeps on the GPU; sampled
     walkers are replayed one by one by the oracle (same global id)."""
     wl = W.WORKLOADS[name]
     groups = wl["groups"]
     sweeps = 1
-    say("full size", name, groups)
-    ctx = M.Context(groups, wl["seed"])
+    say("full size", name, groups, variant)
+    ctx = make_ctx(groups, wl["seed"], variant)
     lnW = W.random_lnW(ctx.total_bins, seed=12, scale=0.5)
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
     ctx.sweep(dev_f64(lnW), sweeps, H)
@@ -331,3 +354,23 @@ def test_determinism_two_contexts():
         outs.append(H.cpu().numpy())
         ctx.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_layouts_and_autotune_give_identical_results():
+    groups = W.scaled("batched_2d", walkers_per_group=40)["groups"] + [(3, 16, 205, 20)]
+    outs = []
+    for variant in VARIANTS + [None]:
+        ctx = make_ctx(groups, 3, variant)
+        lnW = dev_f64(W.random_lnW(ctx.total_bins, seed=21, scale=0.4))
+        H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+        if variant is None:
+            chosen, ms = ctx.autotune(lnW, probe_sweeps=2)
+            say("autotune chose", chosen, ms)
+            assert chosen in M.LAYOUTS and ctx.layout() == chosen
+        ctx.sweep(lnW, 6, H)
+        states = [ctx.read_walker(w) for w in range(0, ctx.nwalkers, 7)]
+        outs.append((H.cpu().numpy(), states))
+        ctx.close()
+    for H, st in outs[1:]:
+        assert np.array_equal(H, outs[0][0])
+        assert st == outs[0][1]
