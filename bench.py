@@ -47,6 +47,28 @@ def philox_blocks_per_attempt(groups):
     return acc / tot
 
 
+def measured_traffic(workload, kernel_layout):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs
+    (profiles/sweep_traffic.json), or None when the kernel source has changed
+    since the counters were taken or another kernel ran."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload)
+    if not rec:
+        return None
+    csrc = os.path.join(ROOT, "paper_1401_4076_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, n), "rb").read()
+                   for n in ("muca_sweep_sub.hip", "muca_device.h"))
+    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    want = {2: "k_sweep_sub<16", 3: "k_sweep_sub<64"}.get(kernel_layout)
+    if want is None or want not in rec["kernel"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(groups, seed, sample_sweeps):
     import oracle as O
     ref = O.RefContext(groups, seed)
@@ -81,7 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched_2d", choices=sorted(W.WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=None, help="sweeps per iteration")
-    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 lane, 2 wave")
+    ap.add_argument("--layout", type=int, default=0,
+                    help="0: autotune, 1: lane, 2: 16 lanes/walker, 3: 64 lanes/walker")
+    ap.add_argument("--probe-sweeps", type=int, default=20, help="autotune probe length")
     ap.add_argument("--cpu-sweeps", type=int, default=None,
                     help="sweeps of the CPU oracle sample (default: ~10 s of work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -105,9 +129,16 @@ def main():
     print(f"bench: workload={args.workload} groups={groups} sweeps={sweeps} "
           f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     ctx = M.Context(groups, seed)
-    ctx.set_layout(args.layout)
     dev = torch.device("cuda")
     lnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device=dev)
+    tune_ms = None
+    if args.layout == 0:
+        # state-preserving: the probes do not change any later result
+        chosen, tune_ms = ctx.autotune(lnW, probe_sweeps=min(args.probe_sweeps, sweeps))
+        print(f"bench: autotune chose layout {chosen} (probe ms per layout {tune_ms[1:]})",
+              file=sys.stderr, flush=True)
+    else:
+        ctx.set_layout(args.layout)
     P = torch.zeros_like(lnW)
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
     flags = torch.zeros(ctx.ngroups, dtype=torch.int32, device=dev)
@@ -161,11 +192,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "groups": [list(g) for g in groups],
                    "walkers": sum(g[3] for g in groups), "sweeps_per_iter": sweeps,
-                   "attempts_per_step": per_step, "rule": "berg", "layout": ctx.layout()},
+                   "attempts_per_step": per_step, "rule": "berg", "layout": ctx.layout(),
+                   "autotune_probe_ms": tune_ms},
         "sweep_kernel_ms": sweep_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS,
                      "unit": "int32 lane-op/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": None},
+                     "traffic": measured_traffic(args.workload, ctx.layout())},
     }
     if not args.no_cpu_baseline:
         cs = args.cpu_sweeps

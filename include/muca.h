@@ -189,10 +189,17 @@ int mucaIsFlat(muca_ctx ctx, const int32_t* H, int32_t* flags, void* stream);
  *     H keeps H^i, iters[g] = i + 1, flat[g] = 1.  Groups not flat after
  *     max_iters keep lnW^{max_iters}, H^{max_iters - 1}, flat[g] = 0, and the
  *     call returns MUCA_NOT_CONVERGED.
- * The per-iteration work is captured once as a HIP graph and replayed. */
+ * The per-iteration work (thresholds, sweep, loop control, recursion) is
+ * captured once as a HIP graph on an internal stream, ordered after the
+ * caller's stream, and replayed; the graph is kept for later calls with the
+ * same pointers and parameters. */
 int mucaRun(muca_ctx ctx, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
             int max_iters, int rule, int stop_on_flat, int32_t* iters, int32_t* flat,
             void* stream);
+
+/* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's
+ * stream instead of replaying the captured graph (same results). */
+int mucaSetGraph(muca_ctx ctx, int enable);
 
 /* Copy one walker's state to host memory (waits for the device):
  * occupation bits (ceil(V/32) words, site s = x + L y + L^2 z is bit s%32 of

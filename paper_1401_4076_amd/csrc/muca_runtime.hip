@@ -131,6 +131,21 @@ struct muca_context {
     size_t need = 0;       // LDS bytes for the walker state of the largest block
   } coop[2];               // [0]: 16 lanes per walker, [1]: 64 lanes per walker
   size_t tbl_bytes = 0;    // largest threshold table of one group
+  size_t hist_bytes = 0;   // largest histogram of one group
+  // captured iteration of mucaRun (replayed once per iteration)
+  bool use_graph = true;
+  hipStream_t run_stream = nullptr;  // default priority
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  struct GraphKey {
+    const void *lnW, *P, *H;
+    int sweeps, rule, stop, layout;
+    size_t lds_limit;
+    bool operator==(const GraphKey& o) const {
+      return lnW == o.lnW && P == o.P && H == o.H && sweeps == o.sweeps && rule == o.rule &&
+             stop == o.stop && layout == o.layout && lds_limit == o.lds_limit;
+    }
+  } graph_key{};
   size_t lds_limit = 160 * 1024;  // LDS a cooperative block may use
   size_t lds_device = 64 * 1024;  // device maximum per block
 
@@ -150,6 +165,9 @@ struct muca_context {
     (void)hipFree(d_iters);
     (void)hipFree(d_counter);
     for (auto& q : coop) (void)hipFree(q.d_tasks);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (run_stream) (void)hipStreamDestroy(run_stream);
     if (h_pinned) (void)hipHostFree(h_pinned);
   }
 };
@@ -190,6 +208,7 @@ int build_coop(muca_ctx c, int which) {
     for (int f = 0; f < g.walkers; f += wpb)
       per[i].push_back(SweepTask{i, g.first_walker + f, std::min(wpb, g.walkers - f), 0});
     need = std::max(need, (size_t)wpb * (size_t)(g.words + 2 * g.N) * sizeof(uint32_t));
+    c->hist_bytes = std::max(c->hist_bytes, (size_t)g.nbins * sizeof(int32_t));
   }
   std::vector<SweepTask> tasks;
   for (size_t r = 0;; ++r) {
@@ -218,18 +237,20 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
   if (int r = build_coop(c, which)) return r;
   const auto& q = c->coop[which];
   const size_t cap = std::min(c->lds_limit, c->lds_device);
-  const bool state_lds = q.need <= cap;
-  const size_t state = state_lds ? q.need : 0;
+  // LDS-resident walker state comes with a block histogram in LDS
+  const bool state_lds = q.need + c->hist_bytes <= cap;
+  const size_t state = state_lds ? q.need + c->hist_bytes : 0;
   const bool tbl_lds = c->lds_limit > 0 && state + c->tbl_bytes <= cap;
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
   const int tbl_words = tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0;
-  auto kern = state_lds ? muca::k_sweep_sub<G, true> : muca::k_sweep_sub<G, false>;
-  if (dyn > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)dyn));
+  auto kern = state_lds ? (tbl_lds ? muca::k_sweep_sub<G, true, true>
+                                   : muca::k_sweep_sub<G, true, false>)
+                        : (tbl_lds ? muca::k_sweep_sub<G, false, true>
+                                   : muca::k_sweep_sub<G, false, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
                      c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active, sweeps,
-                     c->first_id, c->seed32, tbl_words);
+                     c->first_id, c->seed32, tbl_words,
+                     state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0);
   LAUNCH_CHECK();
   return MUCA_OK;
 }
@@ -353,6 +374,15 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
     int v = 0;
     HIP_TRY_DEL(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     c->lds_device = (size_t)v;
+    // allow every cooperative kernel the device's full LDS per block (set
+    // once here, outside any stream capture)
+    const void* kernels[] = {
+        (const void*)muca::k_sweep_sub<16, true, true>,  (const void*)muca::k_sweep_sub<16, true, false>,
+        (const void*)muca::k_sweep_sub<16, false, true>, (const void*)muca::k_sweep_sub<16, false, false>,
+        (const void*)muca::k_sweep_sub<64, true, true>,  (const void*)muca::k_sweep_sub<64, true, false>,
+        (const void*)muca::k_sweep_sub<64, false, true>, (const void*)muca::k_sweep_sub<64, false, false>};
+    for (const void* k : kernels)
+      HIP_TRY_DEL(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v));
   }
 
   std::vector<int32_t> wg((size_t)walkers);
@@ -549,6 +579,12 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
   return MUCA_OK;
 }
 
+int mucaSetGraph(muca_ctx c, int enable) {
+  if (int r = check_ctx(c)) return r;
+  c->use_graph = enable != 0;
+  return MUCA_OK;
+}
+
 int mucaSetLdsLimit(muca_ctx c, int64_t bytes) {
   if (int r = check_ctx(c)) return r;
   if (bytes < 0 || bytes > 160 * 1024) return fail(MUCA_EINVAL, "LDS limit must be in [0, 163840]");
@@ -646,23 +682,73 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
   hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter, 0, 1);
   hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter + 1, G, 1);
   LAUNCH_CHECK();
-  int remaining = G;
-  for (int i = 0; i < max_iters; ++i) {
-    if (int r = enqueue_sweep(c, lnW, sweeps_per_iter, H, c->d_active, s)) return r;
-    hipLaunchKernelGGL(muca::k_control, dim3((unsigned)G), dim3(256), 0, s, c->d_groups, H,
+  // one iteration: thresholds, sweep, loop control, recursion, counter
+  auto enqueue_iteration = [&](hipStream_t st) -> int {
+    if (int r = enqueue_sweep(c, lnW, sweeps_per_iter, H, c->d_active, st)) return r;
+    hipLaunchKernelGGL(muca::k_control, dim3((unsigned)G), dim3(256), 0, st, c->d_groups, H,
                        c->d_active, c->d_flat, c->d_iters, c->d_counter, c->d_counter + 1,
                        stop_on_flat);
-    hipLaunchKernelGGL(muca::k_update, dim3((unsigned)G), dim3(256), 0, s, c->d_groups, H, lnW, P,
+    hipLaunchKernelGGL(muca::k_update, dim3((unsigned)G), dim3(256), 0, st, c->d_groups, H, lnW, P,
                        c->d_slope, rule, c->d_active, c->d_status);
-    hipLaunchKernelGGL(muca::k_bump, dim3(1), dim3(64), 0, s, c->d_counter);
+    hipLaunchKernelGGL(muca::k_bump, dim3(1), dim3(64), 0, st, c->d_counter);
     LAUNCH_CHECK();
+    return MUCA_OK;
+  };
+  hipStream_t rs = s;
+  if (c->use_graph) {
+    if (!c->run_stream) HIP_TRY(hipStreamCreateWithFlags(&c->run_stream, hipStreamNonBlocking));
+    rs = c->run_stream;
+    const muca_context::GraphKey key{lnW, P, H, sweeps_per_iter, rule, stop_on_flat,
+                                     resolved_layout(c), c->lds_limit};
+    if (!c->graph_exec || !(key == c->graph_key)) {
+      if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+      if (c->graph) (void)hipGraphDestroy(c->graph);
+      c->graph_exec = nullptr;
+      c->graph = nullptr;
+      // task tables and kernel attributes are set up outside the capture
+      for (int which = 0; which < 2; ++which)
+        if (int r = build_coop(c, which)) return r;
+      HIP_TRY(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+      const int r = enqueue_iteration(rs);
+      hipGraph_t gr = nullptr;
+      const hipError_t e = hipStreamEndCapture(rs, &gr);
+      if (r) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return r;
+      }
+      HIP_TRY(e);
+      c->graph = gr;
+      HIP_TRY(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+      c->graph_key = key;
+    }
+    // order the internal stream after the caller's work
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev, s));
+    HIP_TRY(hipStreamWaitEvent(rs, ev, 0));
+    HIP_TRY(hipEventDestroy(ev));
+  }
+  int remaining = G;
+  for (int i = 0; i < max_iters; ++i) {
+    if (c->use_graph) {
+      HIP_TRY(hipGraphLaunch(c->graph_exec, rs));
+    } else if (int r = enqueue_iteration(rs)) {
+      return r;
+    }
     if (stop_on_flat) {
       HIP_TRY(hipMemcpyAsync(c->h_pinned, c->d_counter, 2 * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
+                             hipMemcpyDeviceToHost, rs));
+      HIP_TRY(hipStreamSynchronize(rs));
       remaining = c->h_pinned[1];
       if (remaining == 0) break;
     }
+  }
+  if (rs != s) {
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev, rs));
+    HIP_TRY(hipStreamWaitEvent(s, ev, 0));
+    HIP_TRY(hipEventDestroy(ev));
   }
   HIP_TRY(hipMemcpyAsync(iters, c->d_iters, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(flat, c->d_flat, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));

@@ -113,14 +113,13 @@ __device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
 }
 
 // Walker state and per-lane constants of one cooperative walker.
-template <int G, bool kLds>
+template <int G, bool kLds, bool kTbl>
 struct Walker {
   const GroupDesc* g;
   uint32_t* bits;
   uint32_t* plin;
   uint32_t* pxyz;  // LDS mode only
-  const uint32_t* th;  // threshold table in device memory
-  const uint32_t* tl;  // the same table in LDS, or nullptr
+  const uint32_t* th;  // threshold table (LDS copy or device memory)
   int32_t* hist;
   int ls, base, d2, nd;
   uint32_t V, N, key0, seed32, in_sweep;
@@ -128,21 +127,17 @@ struct Walker {
   uint64_t t;
   uint32_t Trow;
   // lane roles of the main gather: [0,2d) nbr(s_o), 2d: c2, 2d+1: c3,
-  // [2d+2, 4d+2) nbr(c2)
+  // [2d+2, 4d+2) nbr(c2) and, when 6d+2 lanes are available (full), also
+  // [4d+2, 6d+2) nbr(c3)
   NbrRole role;
-  bool role_on, role_so, role_c3;
+  bool role_on, role_so, role_c3, full;
   NbrRole role2;  // lanes [0, 2d): nbr of s_n in the second gather
   // batch values of lane ls (attempt t + ls)
   uint32_t b_k, b_u, b_c2, b_c2x, b_c3, b_c3x, b_so, b_sox;
 };
 
-template <int G, bool kLds>
-__device__ __forceinline__ uint32_t trow(const Walker<G, kLds>& W, int i) {
-  return W.tl ? W.tl[i] : W.th[i];
-}
-
-template <int G, bool kLds>
-__device__ __forceinline__ void batch_phase(Walker<G, kLds>& W) {
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void batch_phase(Walker<G, kLds, kTbl>& W) {
   const GroupDesc& g = *W.g;
   const uint64_t tl = W.t + (uint64_t)W.ls;
   const U4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), 0u, 0u, W.key0, W.seed32);
@@ -157,11 +152,11 @@ __device__ __forceinline__ void batch_phase(Walker<G, kLds>& W) {
   else W.b_sox = pack_coords(g, W.b_so);
 }
 
-// One attempt with broadcast values; returns nothing, updates W.
-template <int G, bool kLds>
-__device__ __forceinline__ void attempt(Walker<G, kLds>& W, uint32_t k, uint32_t u, uint32_t c2,
-                                        uint32_t c2x, uint32_t c3, uint32_t c3x, uint32_t so,
-                                        uint32_t sox, uint64_t ta) {
+// One attempt with the broadcast values of attempt ta.
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, uint32_t u,
+                                        uint32_t c2, uint32_t c2x, uint32_t c3, uint32_t c3x,
+                                        uint32_t so, uint32_t sox, uint64_t ta) {
   const GroupDesc& g = *W.g;
   const int d2 = W.d2;
   const uint32_t dmask = (1u << d2) - 1u;
@@ -174,19 +169,15 @@ __device__ __forceinline__ void attempt(Walker<G, kLds>& W, uint32_t k, uint32_t
   const bool occ = W.role_on && ((v >> (site & 31u)) & 1u);
   const bool isso = W.role_on && (site == so);
   const uint32_t m = sub_mask<G>(__ballot(occ), W.base);
-  const uint32_t mx = sub_mask<G>(__ballot(isso), W.base);
+  const uint32_t nm = m & ~sub_mask<G>(__ballot(isso), W.base);  // occupied, not s_o
   const int ko = __popc(m & dmask);
-  uint32_t sn, snx;
-  int kn;
-  if (!((m >> d2) & 1u)) {
-    sn = c2;
-    snx = c2x;
-    kn = __popc((m >> (d2 + 2)) & ~(mx >> (d2 + 2)) & dmask);
-  } else {
-    if (!((m >> (d2 + 1)) & 1u)) {
-      sn = c3;
-      snx = c3x;
-    } else {
+  const bool c2free = !((m >> d2) & 1u);
+  const bool c3free = !((m >> (d2 + 1)) & 1u);
+  uint32_t sn = c2free ? c2 : c3;
+  uint32_t snx = c2free ? c2x : c3x;
+  int kn = __popc((nm >> (c2free ? d2 + 2 : 2 * d2 + 2)) & dmask);
+  if (!c2free && !(W.full && c3free)) {
+    if (!c3free) {
       // both candidates occupied: words 0..3 of blocks 1, 2, ... in order
       uint32_t blk = 0;
       for (;;) {
@@ -201,10 +192,7 @@ __device__ __forceinline__ void attempt(Walker<G, kLds>& W, uint32_t k, uint32_t
         const uint32_t fm = sub_mask<G>(__ballot(fr), W.base) & 0xFu;
         if (fm) {
           const int first = __ffs(fm) - 1;
-          const uint32_t words[4] = {q.x, q.y, q.z, q.w};
-          uint32_t pick = words[0];
-          for (int i = 1; i < 4; ++i)
-            if (i == first) pick = words[i];
+          const uint32_t pick = first == 0 ? q.x : first == 1 ? q.y : first == 2 ? q.z : q.w;
           sn = draw(pick, W.V);
           snx = pack_coords(g, sn);
           break;
@@ -222,54 +210,56 @@ __device__ __forceinline__ void attempt(Walker<G, kLds>& W, uint32_t k, uint32_t
   const int dE = ko - kn;
   // every lane of the threshold row tests u; the entry of dE decides
   const bool ok = (W.ls < W.nd) && accepts(W.Trow, u);
-  const uint32_t am = sub_mask<G>(__ballot(ok), W.base);
-  if ((am >> (dE + d2)) & 1u) {
-    if (W.ls == 0) {
-      st<kLds>(&W.plin[k], sn);
-      if constexpr (kLds) W.pxyz[k] = snx;
-      flip<kLds>(W.bits, so, sn);
-    }
-    if constexpr (!kLds) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (W.b_k == k) {  // later attempts of this batch that chose the same particle
-      W.b_so = sn;
-      W.b_sox = snx;
-    }
-    W.E += dE;
-    if (dE != 0 && W.ls < W.nd) W.Trow = trow(W, (W.E - g.e_lo) * W.nd + W.ls);
+  const bool acc = (sub_mask<G>(__ballot(ok), W.base) >> (dE + d2)) & 1u;
+  if (acc && W.ls == 0) {
+    st<kLds>(&W.plin[k], sn);
+    if constexpr (kLds) W.pxyz[k] = snx;
+    flip<kLds>(W.bits, so, sn);
   }
-  if (++W.in_sweep == W.V) {
-    W.in_sweep = 0;
-    if (W.ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+  if constexpr (!kLds) {
+    if (acc) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   }
+  // later attempts of this batch that chose the same particle see its new site
+  const bool take = acc && (W.b_k == k);
+  W.b_so = take ? sn : W.b_so;
+  W.b_sox = take ? snx : W.b_sox;
+  W.E += acc ? dE : 0;
+  if (acc && dE != 0 && W.ls < W.nd) W.Trow = W.th[(W.E - g.e_lo) * W.nd + W.ls];
+  W.in_sweep += 1;
+  const bool sweep_end = W.in_sweep == W.V;
+  if (sweep_end && W.ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+  W.in_sweep = sweep_end ? 0u : W.in_sweep;
 }
 
-template <int A, int G, bool kLds>
-__device__ __forceinline__ void unrolled16(Walker<G, kLds>& W, int nb) {
+template <int A, int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void unrolled16(Walker<G, kLds, kTbl>& W, int nb) {
   if constexpr (A < 16) {
     if (A < nb) {
-      attempt<G, kLds>(W, row_bcast<A>(W.b_k), row_bcast<A>(W.b_u), row_bcast<A>(W.b_c2),
+      attempt<G, kLds, kTbl>(W, row_bcast<A>(W.b_k), row_bcast<A>(W.b_u), row_bcast<A>(W.b_c2),
                        row_bcast<A>(W.b_c2x), row_bcast<A>(W.b_c3), row_bcast<A>(W.b_c3x),
                        row_bcast<A>(W.b_so), row_bcast<A>(W.b_sox), W.t + (uint64_t)A);
-      unrolled16<A + 1, G, kLds>(W, nb);
+      unrolled16<A + 1, G, kLds, kTbl>(W, nb);
     }
   }
 }
 
 }  // namespace
 
-template <int G, bool kLds>
+template <int G, bool kLds, bool kTbl>
 __global__ void __launch_bounds__(256) k_sweep_sub(
     const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
     uint64_t* __restrict__ gT, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
     const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
-    int tbl_words) {
+    int tbl_words, int hist_words) {
   static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
-  extern __shared__ uint32_t smem[];  // [threshold table (tbl_words)] [walker slots]
+  // LDS: [threshold table (tbl_words)] [block histogram (hist_words, LDS-state mode)]
+  //      [walker slots]
+  extern __shared__ uint32_t smem[];
   const SweepTask task = tasks[blockIdx.x];
   if (active && !active[task.group]) return;  // uniform per block
   const GroupDesc g = groups[task.group];
-  Walker<G, kLds> W;
+  Walker<G, kLds, kTbl> W;
   W.g = &g;
   W.ls = threadIdx.x & (G - 1);
   W.base = (threadIdx.x & 63) & ~(G - 1);
@@ -284,14 +274,16 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   uint32_t* sb = gbits + g.bits_off + j * g.words;
   uint32_t* sp = gpos + g.pos_off + j * g.N;
   // the group's threshold table goes to LDS when the launch reserved room
-  const bool tbl_lds = tbl_words > 0;
-  if (tbl_lds) {
+  if constexpr (kTbl) {
     const uint32_t* src = thr + g.thr_off;
     const int n = g.nbins * g.nd;
     for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = src[i];
   }
+  int32_t* lhist = reinterpret_cast<int32_t*>(smem + tbl_words);
   if constexpr (kLds) {
-    W.bits = smem + (size_t)tbl_words + (size_t)slot * (size_t)(g.words + 2 * g.N);
+    for (int i = threadIdx.x; i < g.nbins; i += blockDim.x) lhist[i] = 0;
+    W.bits = smem + (size_t)tbl_words + (size_t)hist_words +
+             (size_t)slot * (size_t)(g.words + 2 * g.N);
     W.plin = W.bits + g.words;
     W.pxyz = W.plin + g.N;
     if (has) {
@@ -312,32 +304,36 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   if (has) {
     const int d2 = W.d2;
     const int ls = W.ls;
-    W.role_on = ls < 2 * d2 + 2;
+    W.full = 3 * d2 + 2 <= G;
+    const int nroles = W.full ? 3 * d2 + 2 : 2 * d2 + 2;
+    W.role_on = ls < nroles;
     W.role_so = ls < d2;
-    W.role_c3 = ls == d2 + 1;
+    W.role_c3 = (ls == d2 + 1) || (ls >= 2 * d2 + 2 && ls < nroles);
     int dir = -1;
     if (ls < d2) dir = ls;
     else if (ls >= d2 + 2 && ls < 2 * d2 + 2) dir = ls - d2 - 2;
+    else if (ls >= 2 * d2 + 2 && ls < nroles) dir = ls - 2 * d2 - 2;
     W.role = make_role(g, dir);
     W.role2 = make_role(g, ls < d2 ? ls : -1);
-    W.th = thr + g.thr_off;
-    W.tl = tbl_lds ? smem : nullptr;
-    W.hist = H + g.bin_off;
+    if constexpr (kTbl) W.th = smem;
+    else W.th = thr + g.thr_off;
+    if constexpr (kLds) W.hist = lhist;  // summed over the block, flushed at the end
+    else W.hist = H + g.bin_off;
     W.key0 = first_id + (uint32_t)w;
     W.seed32 = seed32;
     W.E = gE[w];
     W.t = gT[w];
-    W.Trow = (ls < W.nd) ? trow(W, (W.E - g.e_lo) * W.nd + ls) : 0u;
+    W.Trow = (ls < W.nd) ? W.th[(W.E - g.e_lo) * W.nd + ls] : 0u;
     W.in_sweep = 0;
     const int64_t total = (int64_t)sweeps * (int64_t)W.V;
     for (int64_t done = 0; done < total; done += G) {
       const int nb = (int)((total - done) < G ? (total - done) : G);
       batch_phase<G, kLds>(W);
       if constexpr (G == 16) {
-        unrolled16<0, G, kLds>(W, nb);
+        unrolled16<0, G, kLds, kTbl>(W, nb);
       } else {
         for (int a = 0; a < nb; ++a) {
-          attempt<G, kLds>(W, __builtin_amdgcn_readlane(W.b_k, a),
+          attempt<G, kLds, kTbl>(W, __builtin_amdgcn_readlane(W.b_k, a),
                            __builtin_amdgcn_readlane(W.b_u, a),
                            __builtin_amdgcn_readlane(W.b_c2, a),
                            __builtin_amdgcn_readlane(W.b_c2x, a),
@@ -361,24 +357,34 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
       for (int i = W.ls; i < g.words; i += G) sb[i] = W.bits[i];
       for (int i = W.ls; i < g.N; i += G) sp[i] = W.plin[i];
     }
+    for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
+      if (lhist[i]) atomicAdd(&H[g.bin_off + i], lhist[i]);
   }
 }
 
-template __global__ void k_sweep_sub<16, true>(const GroupDesc*, const SweepTask*, uint32_t*,
-                                                uint32_t*, int32_t*, uint64_t*,
-                                                const uint32_t*, int32_t*, const int32_t*, int,
-                                                uint32_t, uint32_t, int);
-template __global__ void k_sweep_sub<16, false>(const GroupDesc*, const SweepTask*, uint32_t*,
-                                                uint32_t*, int32_t*, uint64_t*,
-                                                const uint32_t*, int32_t*, const int32_t*, int,
-                                                uint32_t, uint32_t, int);
-template __global__ void k_sweep_sub<64, true>(const GroupDesc*, const SweepTask*, uint32_t*,
-                                                uint32_t*, int32_t*, uint64_t*,
-                                                const uint32_t*, int32_t*, const int32_t*, int,
-                                                uint32_t, uint32_t, int);
-template __global__ void k_sweep_sub<64, false>(const GroupDesc*, const SweepTask*, uint32_t*,
-                                                uint32_t*, int32_t*, uint64_t*,
-                                                const uint32_t*, int32_t*, const int32_t*, int,
-                                                uint32_t, uint32_t, int);
+template __global__ void k_sweep_sub<16, true, true>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<16, true, false>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<16, false, true>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<16, false, false>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<64, true, true>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<64, true, false>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<64, false, true>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+template __global__ void k_sweep_sub<64, false, false>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
 
 }  // namespace muca

@@ -52,6 +52,7 @@ SIGNATURES = {
     "mucaAutotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _P(ctypes.c_int),
                                     _P(ctypes.c_double), _vp]),
     "mucaSetLdsLimit": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "mucaSetGraph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaThresholdEntries": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
     "mucaBuildThresholds": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaSweep": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
@@ -169,6 +170,9 @@ class Context:
 
     def set_lds_limit(self, nbytes):
         _check(lib().mucaSetLdsLimit(self._h, int(nbytes)))
+
+    def set_graph(self, enable):
+        _check(lib().mucaSetGraph(self._h, 1 if enable else 0))
 
     def autotune(self, lnW, probe_sweeps=1, stream=None):
         """Returns (chosen layout, [ms per layout index 0..3])."""

@@ -145,9 +145,10 @@ def test_flatness_matches_oracle():
 
 # (layout, LDS limit): every kernel variant, with walker state in LDS and in
 # device memory
-VARIANTS = [(M.MUCA_LAYOUT_LANE, 65536), (M.MUCA_LAYOUT_SUB16, 65536), (M.MUCA_LAYOUT_SUB16, 0),
-            (M.MUCA_LAYOUT_SUB64, 65536), (M.MUCA_LAYOUT_SUB64, 0)]
-VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm"]
+VARIANTS = [(M.MUCA_LAYOUT_LANE, 163840), (M.MUCA_LAYOUT_SUB16, 163840),
+            (M.MUCA_LAYOUT_SUB16, 0), (M.MUCA_LAYOUT_SUB64, 163840), (M.MUCA_LAYOUT_SUB64, 0),
+            (M.MUCA_LAYOUT_SUB16, 24576)]
+VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm", "sub16-lds24k"]
 
 
 def make_ctx(groups, seed, variant=None, first_id=0):
@@ -374,3 +375,29 @@ def test_layouts_and_autotune_give_identical_results():
     for H, st in outs[1:]:
         assert np.array_equal(H, outs[0][0])
         assert st == outs[0][1]
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
+def test_run_graph_and_eager_match_oracle_across_calls(graph):
+    """mucaRun replays a captured iteration; several calls in a row (with
+    the caller's own work in between) must equal the eager path and the
+    oracle every time."""
+    groups = [(2, 8, 16, 24), (3, 5, 12, 9)]
+    ctx = make_ctx(groups, 13)
+    ctx.set_graph(graph)
+    ref = O.RefContext(groups, 13)
+    glnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device=DEV)
+    gP = torch.zeros_like(glnW)
+    gH = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+    lnW = np.zeros(ctx.total_bins)
+    for call in range(3):
+        scratch = torch.ones(1 << 20, device=DEV) * 2.0  # unrelated eager work
+        rc, it, fl = ctx.run(glnW, gP, gH, 20, 3, 0, False)
+        P = np.zeros(ctx.total_bins)  # mucaRun restarts the accumulator
+        rrc, rH, rit, rfl = ref.run(lnW, P, 20, 3, 0, False)
+        torch.cuda.synchronize()
+        assert float(scratch.sum()) == 2.0 * (1 << 20)
+        assert rc == rrc and list(it) == list(rit)
+        assert np.array_equal(gH.cpu().numpy(), rH), call
+        assert same_f64(glnW.cpu().numpy(), lnW), call
+        assert same_f64(gP.cpu().numpy(), P), call
