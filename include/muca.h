@@ -212,6 +212,51 @@ int mucaReadWalker(muca_ctx ctx, int walker, uint32_t* bits, uint32_t* pos, int3
  * error (MUCA_ENONFINITE) or MUCA_OK.  Clears the pending error. */
 int mucaStatus(muca_ctx ctx, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned initial weights (not part of the paper's method; the recursion
+ * from flat weights is its fallback).  A network maps the features
+ * (2(d - 2.5), L / 64, 10 N / L^d, E / e_lo) of a bin to
+ * y = (lnW(E) - lnW(e_lo)) / N; it is trained on converged weight tables the
+ * iteration produced and proposes lnW for a new lattice.
+ * Architecture 4 -> 128 -> 128 -> 128 -> 1 with SiLU; hidden layers use BF16
+ * weights (round-to-nearest-even copies of FP32 master weights) and BF16
+ * activations with FP32 accumulation; the first layer reads FP32 inputs; the
+ * output layer has FP32 weights.  Loss: mean squared error over the rows;
+ * optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the master weights;
+ * gradients pass straight through the BF16 rounding of activations.
+ * Parameters (FP32, flat, mucaMlpParamCount() of them): W1[128][4] b1[128]
+ * W2[128][128] b2[128] W3[128][128] b3[128] W4[128] b4.
+ * X is rows x 4 FP32 (row-major), T and Y rows FP32; all device pointers.
+ * ------------------------------------------------------------------------ */
+typedef struct muca_mlp* muca_mlp_t;
+
+int mucaMlpParamCount(void);
+/* Allocate a network for up to max_rows rows (parameters unset). */
+int mucaMlpCreate(muca_mlp_t* out, int max_rows);
+int mucaMlpDestroy(muca_mlp_t net);
+/* Host copies of the FP32 master parameters; setting them also clears the
+ * Adam state and refreshes the BF16 copy (synchronous). */
+int mucaMlpSetParams(muca_mlp_t net, const float* params, int n);
+int mucaMlpGetParams(muca_mlp_t net, float* params, int n);
+/* Y = net(X). */
+int mucaMlpForward(muca_mlp_t net, const float* X, int rows, float* Y, void* stream);
+/* Gradient of the loss w.r.t. every parameter (grad: device, ParamCount
+ * floats) and the loss (device float, may be NULL); parameters unchanged. */
+int mucaMlpGradient(muca_mlp_t net, const float* X, const float* T, int rows, float* grad,
+                    float* loss, void* stream);
+/* One full-batch Adam step with learning rate lr; loss (device, may be
+ * NULL) receives the loss before the step. */
+int mucaMlpTrainStep(muca_mlp_t net, const float* X, const float* T, int rows, float lr,
+                     float* loss, void* stream);
+/* Training rows of one group of a context: features X (bins x 4) and, if T
+ * is not NULL, targets T = (lnW(E) - lnW(e_lo)) / N from its weights lnW
+ * (the context's concatenated layout). */
+int mucaMlpTableRows(muca_ctx ctx, int group, const double* lnW, float* X, float* T,
+                     void* stream);
+/* Initial weights of one group from the network: lnW(E) = N y(E) shifted so
+ * that lnW(e_hi) = 0, written into the context's concatenated layout. */
+int mucaMlpPredictWeights(muca_mlp_t net, muca_ctx ctx, int group, double* lnW, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

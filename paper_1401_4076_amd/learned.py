@@ -1,0 +1,126 @@
+"""Learned initial weights: orchestration of the mucaMlp* calls.
+
+1. converge weight tables with the MUCA iteration itself (mucaRun until flat);
+2. build training rows from them (mucaMlpTableRows, one row per bin);
+3. train the network with full-batch Adam steps (mucaMlpTrainStep);
+4. propose lnW for a new lattice (mucaMlpPredictWeights) and compare the
+   iteration started there with the plain recursion from flat weights:
+   iterations and wall time to a flat histogram, and the ln Omega estimates.
+All arithmetic runs in the HIP kernels of libmuca; this module only sequences
+calls and moves small results to the host for reporting.
+"""
+import time
+
+import numpy as np
+import torch
+
+from . import muca as M
+
+
+def converge(groups, seed, sweeps, max_iters, rule=M.MUCA_RULE_BERG, lnW0=None, layout=None,
+             stream=None):
+    """Run the iteration until every group is flat.  Returns a dict with the
+    context, weights, histogram, per-group iterations, flags and wall time."""
+    ctx = M.Context(groups, seed)
+    if layout is not None:
+        ctx.set_layout(layout)
+    dev = torch.device("cuda")
+    lnW = (torch.zeros(ctx.total_bins, dtype=torch.float64, device=dev) if lnW0 is None
+           else lnW0.clone())
+    P = torch.zeros_like(lnW)
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, iters, flat = ctx.run(lnW, P, H, sweeps, max_iters, rule, True, stream=stream)
+    torch.cuda.synchronize()
+    return {"ctx": ctx, "lnW": lnW, "H": H, "iters": iters, "flat": flat,
+            "status": rc, "seconds": time.perf_counter() - t0}
+
+
+def table_rows(ctx, lnW, groups=None):
+    """Features and targets of every bin of the chosen groups (all by default)."""
+    sel = range(ctx.ngroups) if groups is None else groups
+    Xs, Ts = [], []
+    for g in sel:
+        lo, hi, _ = ctx.window(g)
+        nb = hi - lo + 1
+        X = torch.empty((nb, 4), dtype=torch.float32, device="cuda")
+        T = torch.empty(nb, dtype=torch.float32, device="cuda")
+        M.mucaMlpTableRows(ctx, g, lnW, X, T)
+        Xs.append(X)
+        Ts.append(T)
+    return torch.cat(Xs), torch.cat(Ts)
+
+
+def train(net, X, T, steps, lr=2e-3, lr_end=2e-4, log_every=0):
+    """Full-batch Adam with a geometric learning-rate decay; returns losses
+    at the logged steps (device values read back at the end)."""
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    for s in range(steps):
+        lr_s = lr * (lr_end / lr) ** (s / max(1, steps - 1))
+        if log_every and (s % log_every == 0 or s == steps - 1):
+            net.train_step(X, T, lr_s, loss)
+            hist.append((s, loss.clone()))
+        else:
+            net.train_step(X, T, lr_s)
+    torch.cuda.synchronize()
+    return [(s, float(v.item())) for s, v in hist]
+
+
+def predict(net, ctx):
+    """Initial weights for every group of ctx from the network."""
+    lnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device="cuda")
+    for g in range(ctx.ngroups):
+        net.predict_weights(ctx, g, lnW)
+    torch.cuda.synchronize()
+    return lnW
+
+
+def ln_omega(ctx, lnW, H):
+    """ln Omega(E) = ln H(E) - lnW(E) over visited bins of each group, shifted
+    so that the largest value is 0 (host arrays, for reporting)."""
+    lw = lnW.cpu().numpy()
+    h = H.cpu().numpy()
+    out = []
+    for g in range(ctx.ngroups):
+        lo, hi, off = ctx.window(g)
+        sl = slice(off, off + hi - lo + 1)
+        v = np.full(hi - lo + 1, np.nan)
+        seen = h[sl] > 0
+        v[seen] = np.log(h[sl][seen]) - lw[sl][seen]
+        v -= np.nanmax(v)
+        out.append(v)
+    return out
+
+
+def production(run, sweeps):
+    """One equilibrium run with the converged weights (more statistics for
+    the ln Omega estimate); returns the histogram."""
+    H = torch.zeros_like(run["H"])
+    run["ctx"].sweep(run["lnW"], sweeps, H)
+    torch.cuda.synchronize()
+    return H
+
+
+def compare(net, groups, seed, sweeps, max_iters, layout=None, prod_sweeps=0):
+    """Iteration from flat weights vs from the network's proposal.  With
+    prod_sweeps > 0 the ln Omega estimates come from a production run with
+    each arm's converged weights, else from the last histogram."""
+    plain = converge(groups, seed, sweeps, max_iters, layout=layout)
+    probe = M.Context(groups, seed)
+    lnW0 = predict(net, probe)
+    probe.close()
+    learned = converge(groups, seed, sweeps, max_iters, lnW0=lnW0, layout=layout)
+    Hp = production(plain, prod_sweeps) if prod_sweeps else plain["H"]
+    Hl = production(learned, prod_sweeps) if prod_sweeps else learned["H"]
+    lo_p = ln_omega(plain["ctx"], plain["lnW"], Hp)
+    lo_l = ln_omega(learned["ctx"], learned["lnW"], Hl)
+    diffs = []
+    for a, b in zip(lo_p, lo_l):
+        both = ~np.isnan(a) & ~np.isnan(b)
+        d = a[both] - b[both]
+        diffs.append(float(np.max(np.abs(d - d.mean()))) if both.any() else float("nan"))
+    return {"plain": {k: plain[k] for k in ("iters", "flat", "status", "seconds")},
+            "learned": {k: learned[k] for k in ("iters", "flat", "status", "seconds")},
+            "ln_omega_max_abs_diff": diffs}

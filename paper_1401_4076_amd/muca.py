@@ -64,6 +64,16 @@ SIGNATURES = {
     "mucaReadWalker": (ctypes.c_int, [_vp, ctypes.c_int, _P(ctypes.c_uint32),
                                       _P(ctypes.c_uint32), _P(_i32), _P(ctypes.c_uint64)]),
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
+    "mucaMlpParamCount": (ctypes.c_int, []),
+    "mucaMlpCreate": (ctypes.c_int, [_P(_vp), ctypes.c_int]),
+    "mucaMlpDestroy": (ctypes.c_int, [_vp]),
+    "mucaMlpSetParams": (ctypes.c_int, [_vp, _P(ctypes.c_float), ctypes.c_int]),
+    "mucaMlpGetParams": (ctypes.c_int, [_vp, _P(ctypes.c_float), ctypes.c_int]),
+    "mucaMlpForward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
+    "mucaMlpGradient": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp]),
+    "mucaMlpTrainStep": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]),
+    "mucaMlpTableRows": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "mucaMlpPredictWeights": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
 }
 
 
@@ -284,3 +294,74 @@ def mucaReadWalker(ctx, walker):
 
 def mucaDestroy(ctx):
     ctx.close()
+
+
+class Mlp:
+    """The learned-initial-weights network (mucaMlp*).  Tensors are CUDA
+    float32 (features rows x 4, targets / outputs rows)."""
+
+    def __init__(self, max_rows):
+        h = ctypes.c_void_p()
+        _check(lib().mucaMlpCreate(ctypes.byref(h), int(max_rows)))
+        self._h = h
+        self.max_rows = int(max_rows)
+        self.nparams = lib().mucaMlpParamCount()
+
+    def close(self):
+        if self._h:
+            lib().mucaMlpDestroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().mucaMlpSetParams(self._h, p.ctypes.data_as(_P(ctypes.c_float)), p.size))
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().mucaMlpGetParams(self._h, p.ctypes.data_as(_P(ctypes.c_float)), p.size))
+        return p
+
+    def forward(self, X, Y, stream=None):
+        rows = X.shape[0]
+        _check(lib().mucaMlpForward(self._h, _dev(X, torch.float32, rows * 4, "X"), rows,
+                                    _dev(Y, torch.float32, rows, "Y"), _stream(stream)))
+
+    def gradient(self, X, T, grad, loss=None, stream=None):
+        rows = X.shape[0]
+        _check(lib().mucaMlpGradient(self._h, _dev(X, torch.float32, rows * 4, "X"),
+                                     _dev(T, torch.float32, rows, "T"), rows,
+                                     _dev(grad, torch.float32, self.nparams, "grad"),
+                                     None if loss is None else _dev(loss, torch.float32, 1, "loss"),
+                                     _stream(stream)))
+
+    def train_step(self, X, T, lr, loss=None, stream=None):
+        rows = X.shape[0]
+        _check(lib().mucaMlpTrainStep(self._h, _dev(X, torch.float32, rows * 4, "X"),
+                                      _dev(T, torch.float32, rows, "T"), rows, float(lr),
+                                      None if loss is None else _dev(loss, torch.float32, 1,
+                                                                     "loss"),
+                                      _stream(stream)))
+
+    def predict_weights(self, ctx, group, lnW, stream=None):
+        _check(lib().mucaMlpPredictWeights(self._h, ctx.handle, int(group),
+                                           _dev(lnW, torch.float64, ctx.total_bins, "lnW"),
+                                           _stream(stream)))
+
+
+def mucaMlpTableRows(ctx, group, lnW, X, T=None, stream=None):
+    lo, hi, _ = ctx.window(group)
+    nb = hi - lo + 1
+    _check(lib().mucaMlpTableRows(ctx.handle, int(group),
+                                  None if lnW is None else _dev(lnW, torch.float64,
+                                                                ctx.total_bins, "lnW"),
+                                  _dev(X, torch.float32, nb * 4, "X"),
+                                  None if T is None else _dev(T, torch.float32, nb, "T"),
+                                  _stream(stream)))

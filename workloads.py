@@ -88,3 +88,27 @@ def random_histogram(total_bins, seed, high=10_000, zero_frac=0.1):
     h = rng.integers(1, high, total_bins).astype(np.int32)
     h[rng.random(total_bins) < zero_frac] = 0
     return h
+
+
+# Learned-initial-weights network: 4 -> 128 -> 128 -> 128 -> 1 (flat FP32
+# parameter vector W1[128][4] b1 W2[128][128] b2 W3[128][128] b3 W4[128] b4).
+MLP_SIZES = (4, 128, 128, 128, 1)
+
+
+def mlp_init_params(seed):
+    """Seeded initial parameters: weights N(0, 1/fan_in), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in zip(MLP_SIZES[:-1], MLP_SIZES[1:]):
+        parts.append(rng.normal(0.0, 1.0 / np.sqrt(fan_in), (fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_synthetic_rows(n, seed):
+    """Seeded feature rows in the ranges the features take, and a smooth target."""
+    rng = np.random.default_rng(seed)
+    X = np.stack([rng.choice([-1.0, 1.0], n), rng.uniform(0.1, 1.0, n), rng.uniform(0.2, 2.5, n),
+                  rng.uniform(0.0, 1.0, n)], axis=1).astype(np.float32)
+    T = (np.sin(3 * X[:, 3]) * X[:, 2] - 0.5 * X[:, 1] + 0.2 * X[:, 0]).astype(np.float32)
+    return X, T
