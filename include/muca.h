@@ -63,6 +63,8 @@ extern "C" {
 #define MUCA_LAYOUT_LANE 1  /* one walker per lane, walker state in device memory */
 #define MUCA_LAYOUT_SUB16 2 /* 16 lanes per walker (4 walkers per wavefront) */
 #define MUCA_LAYOUT_SUB64 3 /* 64 lanes (one wavefront) per walker */
+#define MUCA_LAYOUT_LOOK4 4 /* one wavefront per walker, four attempts gathered per step
+                               (walker state in LDS; else runs as SUB64) */
 
 typedef struct muca_context* muca_ctx;
 
@@ -128,7 +130,7 @@ int mucaSetLdsLimit(muca_ctx ctx, int64_t bytes);
 /* Time every layout on `probe_sweeps` sweeps with weights lnW (device) and
  * keep the fastest; synchronous.  Walker state is saved before and restored
  * after the probes, so the call does not change any later result.  chosen
- * (host, may be NULL) receives the layout, ms (host, may be NULL, 4 doubles)
+ * (host, may be NULL) receives the layout, ms (host, may be NULL, 5 doubles)
  * the probe time per layout index (0 where not run). */
 int mucaAutotune(muca_ctx ctx, const double* lnW, int probe_sweeps, int* chosen, double* ms,
                  void* stream);
@@ -182,7 +184,11 @@ int mucaIsFlat(muca_ctx ctx, const int32_t* H, int32_t* flags, void* stream);
 
 /* The whole iteration (Sec. 2), synchronous.  lnW, P, H are device
  * pointers; lnW holds the initial weights on entry (flat or learned), P is
- * zeroed by the call.  iters and flat are host arrays of ngroups int32.
+ * zeroed by the call (resume = 0).  resume = 1 continues the previous
+ * mucaRun of this context exactly where it stopped (same P, same finished
+ * groups, iteration count continued), so a long run can be split into
+ * several calls; max_iters then counts the iterations of this call.
+ * iters and flat are host arrays of ngroups int32.
  *   stop_on_flat = 0: exactly max_iters iterations of (sweep, update):
  *     lnW = lnW^K, H = H^{K-1}, flat[g] = flatness of H^{K-1}, iters[g] = K.
  *   stop_on_flat = 1: group g stops at its first flat H^i: lnW keeps lnW^i,
@@ -194,8 +200,8 @@ int mucaIsFlat(muca_ctx ctx, const int32_t* H, int32_t* flags, void* stream);
  * caller's stream, and replayed; the graph is kept for later calls with the
  * same pointers and parameters. */
 int mucaRun(muca_ctx ctx, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
-            int max_iters, int rule, int stop_on_flat, int32_t* iters, int32_t* flat,
-            void* stream);
+            int max_iters, int rule, int stop_on_flat, int resume, int32_t* iters,
+            int32_t* flat, void* stream);
 
 /* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's
  * stream instead of replaying the captured graph (same results). */

@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmuca.so")
-SOURCES = ["muca_kernels.hip", "muca_sweep_sub.hip", "muca_runtime.hip", "muca_mlp.hip",
+SOURCES = ["muca_kernels.hip", "muca_sweep_sub.hip", "muca_sweep_look.hip", "muca_runtime.hip",
+           "muca_mlp.hip",
            "muca_mlp_host.hip"]
 ARCH = os.environ.get("MUCA_OFFLOAD_ARCH", "gfx950")
 

@@ -51,6 +51,7 @@ struct muca_context {
   size_t hist_bytes = 0;   // largest histogram of one group
   // captured iteration of mucaRun (replayed once per iteration)
   bool use_graph = true;
+  bool run_started = false;  // a mucaRun has initialised the loop state
   hipStream_t run_stream = nullptr;  // default priority
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;

@@ -21,6 +21,11 @@ __global__ void k_sweep_sub(const GroupDesc* groups, const SweepTask* tasks, uin
                             uint32_t* gpos, int32_t* gE, uint64_t* gT, const uint32_t* thr,
                             int32_t* H, const int32_t* active, int sweeps, uint32_t first_id,
                             uint32_t seed32, int tbl_words, int hist_words);
+template <bool kTbl>
+__global__ void k_sweep_look(const GroupDesc* groups, const SweepTask* tasks, uint32_t* gbits,
+                             uint32_t* gpos, int32_t* gE, uint64_t* gT, const uint32_t* thr,
+                             int32_t* H, const int32_t* active, int sweeps, uint32_t first_id,
+                             uint32_t seed32, int tbl_words, int hist_words);
 __global__ void k_update(const GroupDesc* groups, const int32_t* H, double* lnW, double* P,
                          double* slope, int rule, const int32_t* active, int32_t* status);
 __global__ void k_flat(const GroupDesc* groups, const int32_t* H, int32_t* flags);

@@ -192,6 +192,25 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
   return MUCA_OK;
 }
 
+// Lookahead layout: blocks of four walkers (one per wavefront), walker state
+// and block histogram in LDS; falls back to SUB64 when they do not fit.
+int launch_look(muca_ctx c, int sweeps, int32_t* H, const int32_t* active, hipStream_t s) {
+  if (int r = build_coop(c, 1)) return r;
+  const auto& q = c->coop[1];
+  const size_t cap = std::min(c->lds_limit, c->lds_device);
+  if (q.need + c->hist_bytes > cap) return launch_coop<64>(c, 1, sweeps, H, active, s);
+  const size_t state = q.need + c->hist_bytes;
+  const bool tbl_lds = state + c->tbl_bytes <= cap;
+  const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
+  auto kern = tbl_lds ? muca::k_sweep_look<true> : muca::k_sweep_look<false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
+                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active, sweeps,
+                     c->first_id, c->seed32, tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0,
+                     (int)(c->hist_bytes / sizeof(int32_t)));
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
 int enqueue_sweep_kernel(muca_ctx c, int layout, int sweeps, int32_t* H, const int32_t* active,
                          hipStream_t s) {
   switch (layout) {
@@ -205,6 +224,8 @@ int enqueue_sweep_kernel(muca_ctx c, int layout, int sweeps, int32_t* H, const i
       return launch_coop<16>(c, 0, sweeps, H, active, s);
     case MUCA_LAYOUT_SUB64:
       return launch_coop<64>(c, 1, sweeps, H, active, s);
+    case MUCA_LAYOUT_LOOK4:
+      return launch_look(c, sweeps, H, active, s);
     default:
       return fail(MUCA_EINVAL, "unknown layout %d", layout);
   }
@@ -317,7 +338,8 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
         (const void*)muca::k_sweep_sub<16, true, true>,  (const void*)muca::k_sweep_sub<16, true, false>,
         (const void*)muca::k_sweep_sub<16, false, true>, (const void*)muca::k_sweep_sub<16, false, false>,
         (const void*)muca::k_sweep_sub<64, true, true>,  (const void*)muca::k_sweep_sub<64, true, false>,
-        (const void*)muca::k_sweep_sub<64, false, true>, (const void*)muca::k_sweep_sub<64, false, false>};
+        (const void*)muca::k_sweep_sub<64, false, true>, (const void*)muca::k_sweep_sub<64, false, false>,
+        (const void*)muca::k_sweep_look<true>, (const void*)muca::k_sweep_look<false>};
     for (const void* k : kernels)
       HIP_TRY_DEL(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v));
   }
@@ -431,7 +453,7 @@ int mucaGetWindow(muca_ctx c, int group, int32_t* e_lo, int32_t* e_hi, int32_t* 
 
 int mucaSetLayout(muca_ctx c, int layout) {
   if (int r = check_ctx(c)) return r;
-  if (layout < MUCA_LAYOUT_AUTO || layout > MUCA_LAYOUT_SUB64)
+  if (layout < MUCA_LAYOUT_AUTO || layout > MUCA_LAYOUT_LOOK4)
     return fail(MUCA_EINVAL, "unknown layout %d", layout);
   c->layout = layout;
   return MUCA_OK;
@@ -482,7 +504,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     HIP_TRY(hipEventCreate(&ev1));
     if ((r = save(false))) return r;
     if ((r = enqueue_thresholds(c, lnW, s))) return r;
-    for (int lay = MUCA_LAYOUT_LANE; lay <= MUCA_LAYOUT_SUB64; ++lay) {
+    for (int lay = MUCA_LAYOUT_LANE; lay <= MUCA_LAYOUT_LOOK4; ++lay) {
       if ((r = enqueue_zero_hist(c, h, c->d_ones, s))) return r;
       HIP_TRY(hipEventRecord(ev0, s));
       if ((r = enqueue_sweep_kernel(c, lay, probe_sweeps, h, c->d_ones, s))) return r;
@@ -501,7 +523,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     return MUCA_OK;
   };
   if (ms)
-    for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+    for (int i = 0; i < 5; ++i) ms[i] = 0.0;
   rc = body();
   (void)hipFree(b0);
   (void)hipFree(p0);
@@ -600,7 +622,8 @@ int mucaStatus(muca_ctx c, void* stream) {
 }
 
 int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter, int max_iters,
-            int rule, int stop_on_flat, int32_t* iters, int32_t* flat, void* stream) {
+            int rule, int stop_on_flat, int resume, int32_t* iters, int32_t* flat,
+            void* stream) {
   if (int r = check_ctx(c)) return r;
   if (!lnW || !P || !H || !iters || !flat)
     return fail(MUCA_EINVAL, "lnW, P, H, iters and flat must not be NULL");
@@ -611,14 +634,20 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const int G = c->ngroups;
-  hipLaunchKernelGGL(muca::k_fill_f64, dim3((unsigned)std::min(1024, (c->total_bins + 255) / 256)),
-                     dim3(256), 0, s, P, 0.0, c->total_bins);
-  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_active, 1, G);
-  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_flat, 0, G);
-  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_iters, 0, G);
-  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter, 0, 1);
-  hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter + 1, G, 1);
-  LAUNCH_CHECK();
+  if (resume && !c->run_started)
+    return fail(MUCA_EINVAL, "resume without a previous mucaRun on this context");
+  if (!resume) {
+    hipLaunchKernelGGL(muca::k_fill_f64,
+                       dim3((unsigned)std::min(1024, (c->total_bins + 255) / 256)), dim3(256), 0,
+                       s, P, 0.0, c->total_bins);
+    hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_active, 1, G);
+    hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_flat, 0, G);
+    hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, s, c->d_iters, 0, G);
+    hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter, 0, 1);
+    hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(64), 0, s, c->d_counter + 1, G, 1);
+    LAUNCH_CHECK();
+    c->run_started = true;
+  }
   // one iteration: thresholds, sweep, loop control, recursion, counter
   auto enqueue_iteration = [&](hipStream_t st) -> int {
     if (int r = enqueue_sweep(c, lnW, sweeps_per_iter, H, c->d_active, st)) return r;
@@ -666,7 +695,13 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
     HIP_TRY(hipEventDestroy(ev));
   }
   int remaining = G;
-  for (int i = 0; i < max_iters; ++i) {
+  if (resume) {  // groups already flat stay finished
+    HIP_TRY(hipMemcpyAsync(c->h_pinned, c->d_counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    remaining = c->h_pinned[1];
+  }
+  for (int i = 0; i < max_iters && remaining > 0; ++i) {
     if (c->use_graph) {
       HIP_TRY(hipGraphLaunch(c->graph_exec, rs));
     } else if (int r = enqueue_iteration(rs)) {

@@ -18,9 +18,13 @@ from . import muca as M
 
 
 def converge(groups, seed, sweeps, max_iters, rule=M.MUCA_RULE_BERG, lnW0=None, layout=None,
-             stream=None):
-    """Run the iteration until every group is flat.  Returns a dict with the
-    context, weights, histogram, per-group iterations, flags and wall time."""
+             stream=None, chunk=0, progress=None, max_seconds=None):
+    """Run the iteration until every group is flat (at most max_iters).
+    chunk > 0 splits the run into resumed calls of `chunk` iterations (same
+    result), calls progress(done_iterations, flat_flags, seconds) after each
+    and stops early once max_seconds have passed (status not converged).
+    Returns a dict with the context, weights, histogram, per-group
+    iterations, flags, status and wall time."""
     ctx = M.Context(groups, seed)
     if layout is not None:
         ctx.set_layout(layout)
@@ -31,7 +35,19 @@ def converge(groups, seed, sweeps, max_iters, rule=M.MUCA_RULE_BERG, lnW0=None, 
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, iters, flat = ctx.run(lnW, P, H, sweeps, max_iters, rule, True, stream=stream)
+    step = chunk if chunk > 0 else max_iters
+    done = 0
+    while True:
+        n = min(step, max_iters - done)
+        rc, iters, flat = ctx.run(lnW, P, H, sweeps, n, rule, True, stream=stream,
+                                  resume=done > 0)
+        done += n
+        if progress:
+            progress(done, flat, time.perf_counter() - t0)
+        if rc == M.MUCA_OK or done >= max_iters:
+            break
+        if max_seconds is not None and time.perf_counter() - t0 > max_seconds:
+            break
     torch.cuda.synchronize()
     return {"ctx": ctx, "lnW": lnW, "H": H, "iters": iters, "flat": flat,
             "status": rc, "seconds": time.perf_counter() - t0}
@@ -103,15 +119,23 @@ def production(run, sweeps):
     return H
 
 
-def compare(net, groups, seed, sweeps, max_iters, layout=None, prod_sweeps=0):
+def compare(net, groups, seed, sweeps, max_iters, layout=None, prod_sweeps=0, chunk=0,
+            progress=None, max_seconds=None):
     """Iteration from flat weights vs from the network's proposal.  With
     prod_sweeps > 0 the ln Omega estimates come from a production run with
     each arm's converged weights, else from the last histogram."""
-    plain = converge(groups, seed, sweeps, max_iters, layout=layout)
+    t0 = time.perf_counter()
     probe = M.Context(groups, seed)
     lnW0 = predict(net, probe)
     probe.close()
-    learned = converge(groups, seed, sweeps, max_iters, lnW0=lnW0, layout=layout)
+    infer_s = time.perf_counter() - t0
+    learned = converge(groups, seed, sweeps, max_iters, lnW0=lnW0, layout=layout, chunk=chunk,
+                       progress=(lambda *a: progress("learned", *a)) if progress else None,
+                       max_seconds=max_seconds)
+    learned["seconds"] += infer_s  # the learned arm includes the network's inference
+    plain = converge(groups, seed, sweeps, max_iters, layout=layout, chunk=chunk,
+                     progress=(lambda *a: progress("plain", *a)) if progress else None,
+                     max_seconds=max_seconds)
     Hp = production(plain, prod_sweeps) if prod_sweeps else plain["H"]
     Hl = production(learned, prod_sweeps) if prod_sweeps else learned["H"]
     lo_p = ln_omega(plain["ctx"], plain["lnW"], Hp)

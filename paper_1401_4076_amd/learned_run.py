@@ -1,0 +1,119 @@
+"""Learned vs plain initial weights on a target lattice (command line).
+
+Trains the network on converged weight tables the iteration produces for
+the training workloads (default: plain_2d, batched_2d, cubic_3d, each with
+the given walkers per group and sweeps), proposes initial weights for the
+target (default large_3d: 3D L=48, rho=0.03, N=3318) and runs the iteration
+from the proposal and from flat weights until the histogram is flat.
+Prints progress to stderr and one JSON line: iterations and wall time to a
+flat histogram per arm (the learned arm includes inference), and the largest
+difference of the two ln Omega estimates after a production run.  The two
+stages can run apart: --stage train --net FILE saves the trained parameters
+(float32 .npy), --stage eval --net FILE loads them.
+
+    python -m paper_1401_4076_amd.learned_run --target-walkers 1024 --target-sweeps 10
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import workloads as W  # noqa: E402
+from paper_1401_4076_amd import learned as LR  # noqa: E402
+from paper_1401_4076_amd import muca as M  # noqa: E402
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", default="plain_2d,batched_2d,cubic_3d")
+    ap.add_argument("--train-walkers", type=int, default=None, help="walkers per group cap (default: full)")
+    ap.add_argument("--train-sweeps", type=int, default=1000)
+    ap.add_argument("--train-max-iters", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=4000, help="Adam steps")
+    ap.add_argument("--target", default="large_3d")
+    ap.add_argument("--target-walkers", type=int, default=None)
+    ap.add_argument("--target-sweeps", type=int, default=None)
+    ap.add_argument("--target-max-iters", type=int, default=400)
+    ap.add_argument("--prod-sweeps", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--stage", choices=("all", "train", "eval"), default="all")
+    ap.add_argument("--net", default=None, help="parameter file (.npy) to save or load")
+    ap.add_argument("--max-seconds", type=float, default=None,
+                    help="wall-time budget of each iteration run (stops between chunks)")
+    args = ap.parse_args()
+    if args.stage != "all" and not args.net:
+        ap.error("--stage train/eval needs --net")
+
+    out = {"stage": args.stage}
+    if args.stage == "eval":
+        net = M.Mlp(16384)
+        net.set_params(np.load(args.net).astype(np.float32))
+    else:
+        net = train_stage(args, out)
+        if args.net:
+            np.save(args.net, net.get_params())
+    if args.stage != "train":
+        eval_stage(args, net, out)
+    print(json.dumps(out), flush=True)
+
+
+def train_stage(args, out):
+    out["train"] = []
+    Xs, Ts = [], []
+    for name in args.train.split(","):
+        wl = W.scaled(name, walkers_per_group=args.train_walkers, sweeps=args.train_sweeps)
+        log(f"train table {name}: groups {wl['groups']} sweeps {wl['sweeps']}")
+        run = LR.converge(wl["groups"], wl["seed"], wl["sweeps"], args.train_max_iters,
+                          chunk=args.chunk, max_seconds=args.max_seconds,
+                          progress=lambda n, f, s, nm=name: log(f"  {nm}: {n} iterations, "
+                                                                f"flat {list(f)}, {s:.1f} s"))
+        done = [g for g, f in enumerate(run["flat"]) if f]
+        out["train"].append({"workload": name, "groups": [list(g) for g in wl["groups"]],
+                             "sweeps": wl["sweeps"], "iters": list(run["iters"]),
+                             "flat": list(run["flat"]), "seconds": run["seconds"]})
+        if done:
+            X, T = LR.table_rows(run["ctx"], run["lnW"], done)
+            Xs.append(X)
+            Ts.append(T)
+        run["ctx"].close()
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    out["train_rows"] = int(X.shape[0])
+    net = M.Mlp(max(X.shape[0], 16384))
+    net.set_params(W.mlp_init_params(args.seed))
+    t0 = time.perf_counter()
+    hist = LR.train(net, X, T, args.steps, log_every=max(1, args.steps // 8))
+    out["train_seconds"] = time.perf_counter() - t0
+    out["loss"] = hist
+    log(f"trained {args.steps} steps on {X.shape[0]} rows: loss {hist}")
+    return net
+
+
+def eval_stage(args, net, out):
+    out["target"] = args.target
+    wl = W.scaled(args.target, walkers_per_group=args.target_walkers, sweeps=args.target_sweeps)
+    out["target_groups"] = [list(g) for g in wl["groups"]]
+    out["target_sweeps"] = wl["sweeps"]
+    log(f"target {args.target}: groups {wl['groups']} sweeps {wl['sweeps']}")
+    res = LR.compare(net, wl["groups"], wl["seed"], wl["sweeps"], args.target_max_iters,
+                     prod_sweeps=args.prod_sweeps, chunk=args.chunk,
+                     max_seconds=args.max_seconds,
+                     progress=lambda arm, n, f, s: log(f"  {arm}: {n} iterations, flat {list(f)}, "
+                                                       f"{s:.1f} s"))
+    out.update(res)
+
+
+if __name__ == "__main__":
+    main()

@@ -28,7 +28,8 @@ MUCA_LAYOUT_AUTO = 0
 MUCA_LAYOUT_LANE = 1
 MUCA_LAYOUT_SUB16 = 2
 MUCA_LAYOUT_SUB64 = 3
-LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64)
+MUCA_LAYOUT_LOOK4 = 4
+LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64, MUCA_LAYOUT_LOOK4)
 
 # C ABI: name -> (restype, argtypes)
 _P = ctypes.POINTER
@@ -60,7 +61,7 @@ SIGNATURES = {
     "mucaUpdateWeights": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "mucaIsFlat": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaRun": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                               ctypes.c_int, _P(_i32), _P(_i32), _vp]),
+                               ctypes.c_int, ctypes.c_int, _P(_i32), _P(_i32), _vp]),
     "mucaReadWalker": (ctypes.c_int, [_vp, ctypes.c_int, _P(ctypes.c_uint32),
                                       _P(ctypes.c_uint32), _P(_i32), _P(ctypes.c_uint64)]),
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
@@ -185,9 +186,9 @@ class Context:
         _check(lib().mucaSetGraph(self._h, 1 if enable else 0))
 
     def autotune(self, lnW, probe_sweeps=1, stream=None):
-        """Returns (chosen layout, [ms per layout index 0..3])."""
+        """Returns (chosen layout, [ms per layout index 0..4])."""
         ch = ctypes.c_int()
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * 5)()
         _check(lib().mucaAutotune(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
                                   int(probe_sweeps), ctypes.byref(ch), ms, _stream(stream)))
         return ch.value, list(ms)
@@ -218,15 +219,15 @@ class Context:
                                 _stream(stream)))
 
     def run(self, lnW, P, H, sweeps, max_iters, rule=MUCA_RULE_BERG, stop_on_flat=False,
-            stream=None):
+            stream=None, resume=False):
         """Returns (status, iters[list], flat[list])."""
         it = (_i32 * self.ngroups)()
         fl = (_i32 * self.ngroups)()
         rc = _check(lib().mucaRun(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
                                   _dev(P, torch.float64, self.total_bins, "P"),
                                   _dev(H, torch.int32, self.total_bins, "H"), int(sweeps),
-                                  int(max_iters), int(rule), 1 if stop_on_flat else 0, it, fl,
-                                  _stream(stream)))
+                                  int(max_iters), int(rule), 1 if stop_on_flat else 0,
+                                  1 if resume else 0, it, fl, _stream(stream)))
         return rc, list(it), list(fl)
 
     def status(self, stream=None):
@@ -284,8 +285,8 @@ def mucaBuildThresholds(ctx, lnW, out=None, stream=None):
 
 
 def mucaRun(ctx, lnW, P, H, sweeps_per_iter, max_iters, rule=MUCA_RULE_BERG, stop_on_flat=False,
-            stream=None):
-    return ctx.run(lnW, P, H, sweeps_per_iter, max_iters, rule, stop_on_flat, stream)
+            stream=None, resume=False):
+    return ctx.run(lnW, P, H, sweeps_per_iter, max_iters, rule, stop_on_flat, stream, resume)
 
 
 def mucaReadWalker(ctx, walker):

@@ -147,8 +147,10 @@ def test_flatness_matches_oracle():
 # device memory
 VARIANTS = [(M.MUCA_LAYOUT_LANE, 163840), (M.MUCA_LAYOUT_SUB16, 163840),
             (M.MUCA_LAYOUT_SUB16, 0), (M.MUCA_LAYOUT_SUB64, 163840), (M.MUCA_LAYOUT_SUB64, 0),
-            (M.MUCA_LAYOUT_SUB16, 24576)]
-VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm", "sub16-lds24k"]
+            (M.MUCA_LAYOUT_SUB16, 24576), (M.MUCA_LAYOUT_LOOK4, 163840),
+            (M.MUCA_LAYOUT_LOOK4, 24576)]
+VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm", "sub16-lds24k",
+               "look4", "look4-lds24k"]
 
 
 def make_ctx(groups, seed, variant=None, first_id=0):
@@ -223,7 +225,8 @@ def _run_both(groups, seed, sweeps, iters, rule=0, stop_on_flat=False, lnW0=None
     return rc, it, fl
 
 
-@pytest.mark.parametrize("variant", [VARIANTS[0], VARIANTS[1]], ids=VARIANT_IDS[:2])
+@pytest.mark.parametrize("variant", [VARIANTS[0], VARIANTS[1], VARIANTS[6]],
+                         ids=[VARIANT_IDS[0], VARIANT_IDS[1], VARIANT_IDS[6]])
 def test_run_plain_2d_full_schedule(variant):
     # 2D L=8, N=16, 64 walkers, 10 iterations x 1e4 sweeps from lnW = 0
     wl = W.WORKLOADS["plain_2d"]
@@ -247,7 +250,7 @@ FLAT_GROUPS = [(2, 4, 5, 64, -5, 0), (2, 6, 10, 16, 0, 0), (3, 4, 4, 16, -4, 0),
                (2, 8, 12, 16, 0, 0), (2, 7, 9, 8, 0, 0)]
 
 
-@pytest.mark.parametrize("variant", VARIANTS[:2], ids=VARIANT_IDS[:2])
+@pytest.mark.parametrize("variant", VARIANTS[:2] + VARIANTS[6:7], ids=VARIANT_IDS[:2] + ["look4"])
 def test_run_until_flat_per_group(variant):
     # the groups go flat at different iterations (2, 4, 3, 7, 10 for this seed)
     rc, it, fl = _run_both(FLAT_GROUPS, 5, 50, 80, rule=0, stop_on_flat=True, variant=variant)
@@ -401,3 +404,28 @@ def test_run_graph_and_eager_match_oracle_across_calls(graph):
         assert np.array_equal(gH.cpu().numpy(), rH), call
         assert same_f64(glnW.cpu().numpy(), lnW), call
         assert same_f64(gP.cpu().numpy(), P), call
+
+
+def test_run_resumed_in_chunks_equals_one_run():
+    """Splitting a flat-terminated run into several resumed calls gives the
+    same weights, histograms and iteration counts as one call (and the
+    oracle)."""
+    rc1, it1, fl1 = _run_both(FLAT_GROUPS, 5, 50, 80, rule=0, stop_on_flat=True)
+    ctx = make_ctx(FLAT_GROUPS, 5)
+    glnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device=DEV)
+    gP = torch.zeros_like(glnW)
+    gH = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+    ref = O.RefContext(FLAT_GROUPS, 5)
+    lnW, P = np.zeros(ctx.total_bins), np.zeros(ctx.total_bins)
+    rrc, rH, rit, rfl = ref.run(lnW, P, 50, 80, 0, True)
+    done = 0
+    rc = None
+    while done < 80:
+        rc, it, fl = ctx.run(glnW, gP, gH, 50, 3, 0, True, resume=done > 0)
+        done += 3
+        if rc == 0:
+            break
+    assert rc == rrc == 0
+    assert list(it) == list(rit) == list(it1) and list(fl) == list(rfl)
+    assert np.array_equal(gH.cpu().numpy(), rH)
+    assert same_f64(glnW.cpu().numpy(), lnW) and same_f64(gP.cpu().numpy(), P)
