@@ -69,18 +69,57 @@ def measured_traffic(workload, kernel_layout):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(groups, seed, sample_sweeps):
+def cpu_threads():
+    """Host cores for the oracle: the process's CPU set, at most 16 (one
+    GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def split_walkers(groups, parts):
+    """Split the global walker ids into `parts` contiguous ranges of about
+    equal work (walkers x L^d); returns (groups of the range, first id) per
+    non-empty range, ids and therefore random streams unchanged."""
+    total = sum(g[3] for g in groups)
+    work = np.concatenate([np.full(g[3], g[1] ** g[0], dtype=np.float64) for g in groups])
+    cum = np.concatenate([[0.0], np.cumsum(work)])
+    cuts = [int(np.searchsorted(cum, cum[-1] * i / parts)) for i in range(parts)] + [total]
+    out = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        sub, first = [], 0
+        for g in groups:
+            lo, hi = max(a, first), min(b, first + g[3])
+            if lo < hi:
+                sub.append(tuple(g[:3]) + (hi - lo,) + tuple(g[4:]))
+            first += g[3]
+        if sub:
+            out.append((sub, a))
+    return out
+
+
+def cpu_baseline(groups, seed, sample_sweeps, threads):
+    """The oracle on the host, one instance per thread over disjoint ranges of
+    global walker ids (the paper's one-process-per-core scheme).  The oracle
+    is C called through ctypes, which releases the GIL, so the instances run
+    in parallel."""
     import oracle as O
-    ref = O.RefContext(groups, seed)
-    lnW = np.zeros(ref.total_bins)
+    from concurrent.futures import ThreadPoolExecutor
+    total = sum(g[3] for g in groups)
+    refs = [O.RefContext(sub, seed, first_id=a) for sub, a in split_walkers(groups, threads)]
+    lnWs = [np.zeros(r.total_bins) for r in refs]
     t0 = time.perf_counter()
-    H = ref.sweep(lnW, sample_sweeps)
+    with ThreadPoolExecutor(len(refs)) as ex:
+        Hs = list(ex.map(lambda i: refs[i].sweep(lnWs[i], sample_sweeps), range(len(refs))))
     dt = time.perf_counter() - t0
     n = attempts_per_sweep(groups) * sample_sweeps
-    assert int(H.sum()) == sum(g[3] for g in groups) * sample_sweeps
-    return {"value": n / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"all {ref.nwalkers} walkers x {sample_sweeps} sweeps "
-                      f"({n:.3g} attempts, flat weights) in {dt:.1f} s, single thread"}
+    assert sum(int(H.sum()) for H in Hs) == total * sample_sweeps
+    return {"value": n / dt, "unit": "attempts/s", "cores": len(refs), "kind": "oracle",
+            "sample": f"all {total} walkers x {sample_sweeps} sweeps ({n:.3g} attempts, flat "
+                      f"weights) in {dt:.1f} s on {len(refs)} threads, one oracle instance per "
+                      f"thread over disjoint walker ranges"}
 
 
 def calibrate_copy(nbytes):
@@ -104,10 +143,12 @@ def main():
     ap.add_argument("--workload", default="batched_2d", choices=sorted(W.WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=None, help="sweeps per iteration")
     ap.add_argument("--layout", type=int, default=0,
-                    help="0: autotune, 1: lane, 2: 16 lanes/walker, 3: 64 lanes/walker")
+                    help="0: autotune, else a MUCA_LAYOUT_* index (1 lane, 2 16 lanes/walker, "
+                         "3 64 lanes/walker, 4 lookahead, 5/6 16 lanes with 2/1 walkers "
+                         "per wavefront)")
     ap.add_argument("--probe-sweeps", type=int, default=20, help="autotune probe length")
     ap.add_argument("--cpu-sweeps", type=int, default=None,
-                    help="sweeps of the CPU oracle sample (default: ~10 s of work)")
+                    help="sweeps of the CPU oracle sample (default: ~4e8 attempts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
@@ -201,11 +242,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         cs = args.cpu_sweeps
-        if cs is None:
-            cs = max(1, int(round(1.2e8 / attempts_per_sweep(groups))))
-        print(f"bench: CPU oracle sample, {cs} sweeps of all walkers", file=sys.stderr,
-              flush=True)
-        out["cpu_baseline"] = cpu_baseline(groups, seed, cs)
+        if cs is None:  # ~4e8 attempts: ~15-20 s of single-core oracle work
+            cs = max(1, int(round(4e8 / attempts_per_sweep(groups))))
+        nt = cpu_threads()
+        print(f"bench: CPU oracle sample, {cs} sweeps of all walkers on {nt} threads",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(groups, seed, cs, nt)
     print(json.dumps(out), flush=True)
 
 

@@ -65,6 +65,10 @@ extern "C" {
 #define MUCA_LAYOUT_SUB64 3 /* 64 lanes (one wavefront) per walker */
 #define MUCA_LAYOUT_LOOK4 4 /* one wavefront per walker, four attempts gathered per step
                                (walker state in LDS; else runs as SUB64) */
+#define MUCA_LAYOUT_SUB16X2 5 /* 16 lanes per walker, 2 walkers per wavefront (more
+                                 wavefronts per SIMD for small populations) */
+#define MUCA_LAYOUT_SUB16X1 6 /* 16 lanes per walker, 1 walker per wavefront */
+#define MUCA_NUM_LAYOUTS 7    /* layout indices 0 .. MUCA_NUM_LAYOUTS - 1 */
 
 typedef struct muca_context* muca_ctx;
 
@@ -78,7 +82,7 @@ typedef struct {
   int32_t L;       /* 3 <= L <= 1024, V = L^d <= 2^24 */
   int32_t N;       /* 1 <= N <= V-1; N <= V/2 for the default window */
   int32_t walkers; /* >= 1 */
-  int32_t e_lo, e_hi; /* -d N <= e_lo <= e_hi <= 0, or both 0 */
+  int32_t e_lo, e_hi; /* -d N <= e_lo <= e_hi <= 0 with at most 2^24 bins, or both 0 */
 } muca_group;
 
 /* Create a context of one group; equivalent to mucaInitGroups with one
@@ -124,14 +128,18 @@ int mucaGetLayout(muca_ctx ctx, int* layout);
  * bits and particle sites of the block's walkers) goes to LDS when it fits,
  * then the group's threshold table when it fits beside it; what does not
  * fit stays in device memory.  Default 163840; 0 keeps everything in device
- * memory. */
+ * memory.  A context with a 3D group of L % 8 == 0 whose 16-walker state
+ * exceeds 163840 bytes keeps that group's bits in 8x8x8 bricks (fewer memory
+ * lines per neighbourhood) and walker state in device memory in every
+ * layout (LOOK4 then runs as SUB64); results are unchanged. */
 int mucaSetLdsLimit(muca_ctx ctx, int64_t bytes);
 
 /* Time every layout on `probe_sweeps` sweeps with weights lnW (device) and
  * keep the fastest; synchronous.  Walker state is saved before and restored
  * after the probes, so the call does not change any later result.  chosen
- * (host, may be NULL) receives the layout, ms (host, may be NULL, 5 doubles)
- * the probe time per layout index (0 where not run). */
+ * (host, may be NULL) receives the layout, ms (host, may be NULL,
+ * MUCA_NUM_LAYOUTS doubles) the probe time per layout index (0 where not
+ * run). */
 int mucaAutotune(muca_ctx ctx, const double* lnW, int probe_sweeps, int* chosen, double* ms,
                  void* stream);
 

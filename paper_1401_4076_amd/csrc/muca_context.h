@@ -17,6 +17,8 @@ namespace muca_detail {
 int fail(int code, const char* fmt, ...);
 }  // namespace muca_detail
 
+constexpr int64_t kLdsBytes = 160 * 1024;  // LDS per CU of gfx950
+
 struct muca_context {
   int device = 0;
   uint32_t seed32 = 0, first_id = 0;
@@ -46,11 +48,12 @@ struct muca_context {
     SweepTask* d_tasks = nullptr;
     int ntasks = 0;
     size_t need = 0;       // LDS bytes for the walker state of the largest block
-  } coop[2];               // [0]: 16 lanes per walker, [1]: 64 lanes per walker
+  } coop[4];  // lanes per walker / walkers per wavefront: [0] 16/4, [1] 64/1, [2] 16/2, [3] 16/1
   size_t tbl_bytes = 0;    // largest threshold table of one group
   size_t hist_bytes = 0;   // largest histogram of one group
   // captured iteration of mucaRun (replayed once per iteration)
   bool use_graph = true;
+  bool bricked = false;  // some group keeps bricked bits (always device-memory state)
   bool run_started = false;  // a mucaRun has initialised the loop state
   hipStream_t run_stream = nullptr;  // default priority
   hipGraph_t graph = nullptr;
@@ -64,7 +67,7 @@ struct muca_context {
              stop == o.stop && layout == o.layout && lds_limit == o.lds_limit;
     }
   } graph_key{};
-  size_t lds_limit = 160 * 1024;  // LDS a cooperative block may use
+  size_t lds_limit = kLdsBytes;  // LDS a cooperative block may use
   size_t lds_device = 64 * 1024;  // device maximum per block
 
   ~muca_context() {

@@ -24,7 +24,7 @@ struct GroupDesc {
   int32_t words;                  // 32-bit occupation words per walker
   int32_t LL;                     // L * L
   float invL;                     // 1/L rounded, used with an exact fix-up
-  int32_t pad_;
+  int32_t brick8;                 // L / 8 for a bricked bit layout, 0 for linear
   int64_t bits_off;               // first occupation word of the group's walker 0
   int64_t pos_off;                // first particle entry of the group's walker 0
 };
@@ -46,8 +46,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
                                      uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint32_t a = 0xD2511F53u * c0, ah = __umulhi(0xD2511F53u, c0);
-    const uint32_t b = 0xCD9E8D57u * c2, bh = __umulhi(0xCD9E8D57u, c2);
+    // one 32x32->64 product gives both halves (a single v_mad_u64_u32)
+    const uint64_t pa = (uint64_t)0xD2511F53u * c0, pb = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t a = (uint32_t)pa, ah = (uint32_t)(pa >> 32);
+    const uint32_t b = (uint32_t)pb, bh = (uint32_t)(pb >> 32);
     c0 = bh ^ c1 ^ k0;
     c1 = b;
     c2 = ah ^ c3 ^ k1;
@@ -69,6 +71,58 @@ __device__ __forceinline__ uint32_t div_L(uint32_t s, int32_t L, float invL) {
   q += (r >= L) ? 1 : 0;
   q -= (r < 0) ? 1 : 0;
   return (uint32_t)q;
+}
+
+// Packed coordinates x | y << 10 | z << 20 of site s = x + L y + L^2 z.
+constexpr uint32_t kXyzBits = 10;
+constexpr uint32_t kXyzMask = (1u << kXyzBits) - 1u;
+
+__device__ __forceinline__ uint32_t site_xyz(const GroupDesc& g, uint32_t s) {
+  const uint32_t q = div_L(s, g.L, g.invL);
+  const uint32_t x = s - q * (uint32_t)g.L;
+  if (g.d == 2) return x | (q << kXyzBits);
+  const uint32_t z = div_L(q, g.L, g.invL);
+  const uint32_t y = q - z * (uint32_t)g.L;
+  return x | (y << kXyzBits) | (z << (2 * kXyzBits));
+}
+
+// ---------------------------------------------------------------- bit layout
+// Where the occupation bit of a site lives in a walker's bit array.
+// Linear: bit s % 32 of word s / 32.  Bricked (3D groups with L % 8 == 0
+// whose state is too large for LDS, brick8 = L / 8): 8x8x8 bricks of 512
+// bits (16 words, 64 bytes) in x-fastest brick order, inside a brick x
+// fastest, then y, then z.  A site and its six neighbours then share one
+// brick unless a neighbour crosses a face, where the linear layout puts the
+// z neighbours 2 L^2 / 8 bytes apart: fewer lines fetched per gather.
+struct BitRef {
+  uint32_t word, bit;
+};
+
+__device__ __forceinline__ BitRef bit_ref(const GroupDesc& g, uint32_t s, uint32_t xyz) {
+  if (g.brick8 == 0) return BitRef{s >> 5, s & 31u};
+  const uint32_t x = xyz & kXyzMask, y = (xyz >> kXyzBits) & kXyzMask, z = xyz >> (2 * kXyzBits);
+  const uint32_t nb = (uint32_t)g.brick8;
+  const uint32_t b = ((z >> 3) * nb + (y >> 3)) * nb + (x >> 3);
+  return BitRef{(b << 4) | ((z & 7u) << 1) | ((y & 7u) >> 2), (x & 7u) | ((y & 3u) << 3)};
+}
+
+__device__ __forceinline__ BitRef bit_of(const GroupDesc& g, uint32_t s) {
+  if (g.brick8 == 0) return BitRef{s >> 5, s & 31u};
+  return bit_ref(g, s, site_xyz(g, s));
+}
+
+// Occupation of site s in a walker's bit array, and the two single-bit updates.
+__device__ __forceinline__ uint32_t occupied(const GroupDesc& g, const uint32_t* wb, uint32_t s) {
+  const BitRef r = bit_of(g, s);
+  return (wb[r.word] >> r.bit) & 1u;
+}
+__device__ __forceinline__ void set_site(const GroupDesc& g, uint32_t* wb, uint32_t s) {
+  const BitRef r = bit_of(g, s);
+  wb[r.word] |= 1u << r.bit;
+}
+__device__ __forceinline__ void clear_site(const GroupDesc& g, uint32_t* wb, uint32_t s) {
+  const BitRef r = bit_of(g, s);
+  wb[r.word] &= ~(1u << r.bit);
 }
 
 // The 2d neighbours of site s on the periodic lattice.

@@ -32,9 +32,8 @@ __global__ void k_init_place(const GroupDesc* __restrict__ groups,
     const uint32_t cand[4] = {r.x, r.y, r.z, r.w};
     for (int c = 0; c < 4 && placed < g.N; ++c) {
       const uint32_t s = draw(cand[c], (uint32_t)g.V);
-      const uint32_t m = 1u << (s & 31u);
-      if (!(wb[s >> 5] & m)) {
-        wb[s >> 5] |= m;
+      if (!occupied(g, wb, s)) {
+        set_site(g, wb, s);
         wp[placed++] = s;
       }
     }
@@ -45,7 +44,7 @@ __global__ void k_init_place(const GroupDesc* __restrict__ groups,
     neighbours(g, wp[k], nb);
     for (int a = 0; a < g.d; ++a) {  // + direction of each axis: each pair once
       const uint32_t q = nb[2 * a];
-      pairs += (wb[q >> 5] >> (q & 31u)) & 1u;
+      pairs += occupied(g, wb, q);
     }
   }
   E[w] = -pairs;
@@ -123,33 +122,33 @@ __global__ void __launch_bounds__(64) k_sweep_lane(
       const uint32_t k = draw(r.x, N);
       const uint32_t so = wp[k];
       uint32_t sn = draw(r.z, V);
-      if ((wb[sn >> 5] >> (sn & 31u)) & 1u) {
+      if (occupied(g, wb, sn)) {
         sn = draw(r.w, V);
         uint32_t blk = 0;
-        while ((wb[sn >> 5] >> (sn & 31u)) & 1u) {
+        while (occupied(g, wb, sn)) {
           blk += 1;
           r = philox(tl, th_, blk, 0u, key0, seed32);
           sn = draw(r.x, V);
-          if (!((wb[sn >> 5] >> (sn & 31u)) & 1u)) break;
+          if (!occupied(g, wb, sn)) break;
           sn = draw(r.y, V);
-          if (!((wb[sn >> 5] >> (sn & 31u)) & 1u)) break;
+          if (!occupied(g, wb, sn)) break;
           sn = draw(r.z, V);
-          if (!((wb[sn >> 5] >> (sn & 31u)) & 1u)) break;
+          if (!occupied(g, wb, sn)) break;
           sn = draw(r.w, V);
         }
       }
       uint32_t nb[6];
       int ko = 0, kn = 0;
       neighbours(g, so, nb);
-      for (int q = 0; q < 2 * g.d; ++q) ko += (wb[nb[q] >> 5] >> (nb[q] & 31u)) & 1u;
+      for (int q = 0; q < 2 * g.d; ++q) ko += occupied(g, wb, nb[q]);
       neighbours(g, sn, nb);
       for (int q = 0; q < 2 * g.d; ++q)
-        kn += (nb[q] != so) ? ((wb[nb[q] >> 5] >> (nb[q] & 31u)) & 1u) : 0u;
+        kn += (nb[q] != so) ? occupied(g, wb, nb[q]) : 0u;
       const int dE = ko - kn;
       const uint32_t Tacc = th[(e - g.e_lo) * g.nd + dE + 2 * g.d];
       if (accepts(Tacc, u)) {
-        wb[so >> 5] &= ~(1u << (so & 31u));
-        wb[sn >> 5] |= 1u << (sn & 31u);
+        clear_site(g, wb, so);
+        set_site(g, wb, sn);
         wp[k] = sn;
         e += dE;
       }

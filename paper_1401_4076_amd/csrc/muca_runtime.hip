@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -133,11 +134,14 @@ int resolved_layout(muca_ctx c) {
 
 // Blocks of 256 threads hold 256/G walkers of one group; the blocks of the
 // groups are interleaved so that every CU receives a mix of lattice sizes.
+constexpr int kCoopLanes[4] = {16, 64, 16, 16};  // lanes per walker
+constexpr int kCoopSpread[4] = {1, 1, 2, 4};     // 16-lane rows per walker row used
+
 int build_coop(muca_ctx c, int which) {
   auto& q = c->coop[which];
   if (q.d_tasks) return MUCA_OK;
-  const int G = which == 0 ? 16 : 64;
-  const int wpb = 256 / G;
+  const int G = kCoopLanes[which];
+  const int wpb = 256 / G / kCoopSpread[which];
   std::vector<std::vector<SweepTask>> per(c->ngroups);
   size_t need = 0;
   for (int i = 0; i < c->ngroups; ++i) {
@@ -175,7 +179,7 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
   const auto& q = c->coop[which];
   const size_t cap = std::min(c->lds_limit, c->lds_device);
   // LDS-resident walker state comes with a block histogram in LDS
-  const bool state_lds = q.need + c->hist_bytes <= cap;
+  const bool state_lds = !c->bricked && q.need + c->hist_bytes <= cap;
   const size_t state = state_lds ? q.need + c->hist_bytes : 0;
   const bool tbl_lds = c->lds_limit > 0 && state + c->tbl_bytes <= cap;
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
@@ -187,7 +191,7 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
   hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
                      c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active, sweeps,
                      c->first_id, c->seed32, tbl_words,
-                     state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0);
+                     state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0, kCoopSpread[which]);
   LAUNCH_CHECK();
   return MUCA_OK;
 }
@@ -198,7 +202,7 @@ int launch_look(muca_ctx c, int sweeps, int32_t* H, const int32_t* active, hipSt
   if (int r = build_coop(c, 1)) return r;
   const auto& q = c->coop[1];
   const size_t cap = std::min(c->lds_limit, c->lds_device);
-  if (q.need + c->hist_bytes > cap) return launch_coop<64>(c, 1, sweeps, H, active, s);
+  if (c->bricked || q.need + c->hist_bytes > cap) return launch_coop<64>(c, 1, sweeps, H, active, s);
   const size_t state = q.need + c->hist_bytes;
   const bool tbl_lds = state + c->tbl_bytes <= cap;
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
@@ -226,6 +230,10 @@ int enqueue_sweep_kernel(muca_ctx c, int layout, int sweeps, int32_t* H, const i
       return launch_coop<64>(c, 1, sweeps, H, active, s);
     case MUCA_LAYOUT_LOOK4:
       return launch_look(c, sweeps, H, active, s);
+    case MUCA_LAYOUT_SUB16X2:
+      return launch_coop<16>(c, 2, sweeps, H, active, s);
+    case MUCA_LAYOUT_SUB16X1:
+      return launch_coop<16>(c, 3, sweeps, H, active, s);
     default:
       return fail(MUCA_EINVAL, "unknown layout %d", layout);
   }
@@ -301,6 +309,7 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
       d.e_hi = q.e_hi;
     }
     d.nbins = d.e_hi - d.e_lo + 1;
+    if (d.nbins > (1 << 24)) return bad("the window must hold at most 2^24 bins");
     d.nd = 4 * q.d + 1;
     d.bin_off = (int32_t)bins;
     d.thr_off = (int32_t)thr;
@@ -309,6 +318,11 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
     d.words = (int32_t)((V + 31) / 32);
     d.LL = q.L * q.L;
     d.invL = 1.0f / (float)q.L;
+    // 3D lattices whose walker state cannot sit in LDS (16 walkers of a
+    // block: bits + two words per particle) keep bricked bits in device
+    // memory (fewer lines per neighbourhood gather; bit_ref on the device).
+    const int64_t state16 = 16 * ((int64_t)d.words + 2 * (int64_t)q.N) * 4;
+    d.brick8 = (q.d == 3 && q.L % 8 == 0 && state16 > kLdsBytes) ? q.L / 8 : 0;
     d.bits_off = words;
     d.pos_off = pos;
     walkers += q.walkers;
@@ -321,6 +335,7 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
       return fail(MUCA_EINVAL, "too many walkers or bins");
     }
     c->g.push_back(d);
+    c->bricked = c->bricked || d.brick8 != 0;
   }
   c->nwalkers = (int)walkers;
   c->total_bins = (int)bins;
@@ -453,7 +468,7 @@ int mucaGetWindow(muca_ctx c, int group, int32_t* e_lo, int32_t* e_hi, int32_t* 
 
 int mucaSetLayout(muca_ctx c, int layout) {
   if (int r = check_ctx(c)) return r;
-  if (layout < MUCA_LAYOUT_AUTO || layout > MUCA_LAYOUT_LOOK4)
+  if (layout < MUCA_LAYOUT_AUTO || layout >= MUCA_NUM_LAYOUTS)
     return fail(MUCA_EINVAL, "unknown layout %d", layout);
   c->layout = layout;
   return MUCA_OK;
@@ -504,7 +519,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     HIP_TRY(hipEventCreate(&ev1));
     if ((r = save(false))) return r;
     if ((r = enqueue_thresholds(c, lnW, s))) return r;
-    for (int lay = MUCA_LAYOUT_LANE; lay <= MUCA_LAYOUT_LOOK4; ++lay) {
+    for (int lay = MUCA_LAYOUT_LANE; lay < MUCA_NUM_LAYOUTS; ++lay) {
       if ((r = enqueue_zero_hist(c, h, c->d_ones, s))) return r;
       HIP_TRY(hipEventRecord(ev0, s));
       if ((r = enqueue_sweep_kernel(c, lay, probe_sweeps, h, c->d_ones, s))) return r;
@@ -523,7 +538,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     return MUCA_OK;
   };
   if (ms)
-    for (int i = 0; i < 5; ++i) ms[i] = 0.0;
+    for (int i = 0; i < MUCA_NUM_LAYOUTS; ++i) ms[i] = 0.0;
   rc = body();
   (void)hipFree(b0);
   (void)hipFree(p0);
@@ -546,7 +561,7 @@ int mucaSetGraph(muca_ctx c, int enable) {
 
 int mucaSetLdsLimit(muca_ctx c, int64_t bytes) {
   if (int r = check_ctx(c)) return r;
-  if (bytes < 0 || bytes > 160 * 1024) return fail(MUCA_EINVAL, "LDS limit must be in [0, 163840]");
+  if (bytes < 0 || bytes > kLdsBytes) return fail(MUCA_EINVAL, "LDS limit must be in [0, 163840]");
   c->lds_limit = (size_t)bytes;
   return MUCA_OK;
 }
@@ -672,7 +687,7 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
       c->graph_exec = nullptr;
       c->graph = nullptr;
       // task tables and kernel attributes are set up outside the capture
-      for (int which = 0; which < 2; ++which)
+      for (int which = 0; which < 4; ++which)
         if (int r = build_coop(c, which)) return r;
       HIP_TRY(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
       const int r = enqueue_iteration(rs);
@@ -737,9 +752,23 @@ int mucaReadWalker(muca_ctx c, int walker, uint32_t* bits, uint32_t* pos, int32_
   while (gi + 1 < c->ngroups && walker >= c->g[gi + 1].first_walker) ++gi;
   const GroupDesc& g = c->g[gi];
   const int64_t j = walker - g.first_walker;
-  if (bits)
+  if (bits) {
     HIP_TRY(hipMemcpy(bits, c->d_bits + g.bits_off + j * g.words, sizeof(uint32_t) * g.words,
                       hipMemcpyDeviceToHost));
+    if (g.brick8) {  // bricked (see bit_ref) -> linear
+      std::vector<uint32_t> raw(bits, bits + g.words);
+      std::fill(bits, bits + g.words, 0u);
+      const uint32_t L = (uint32_t)g.L, nb = (uint32_t)g.brick8;
+      for (uint32_t z = 0, s = 0; z < L; ++z)
+        for (uint32_t y = 0; y < L; ++y)
+          for (uint32_t x = 0; x < L; ++x, ++s) {
+            const uint32_t b = ((z >> 3) * nb + (y >> 3)) * nb + (x >> 3);
+            const uint32_t w = (b << 4) | ((z & 7u) << 1) | ((y & 7u) >> 2);
+            const uint32_t k = (x & 7u) | ((y & 3u) << 3);
+            if ((raw[w] >> k) & 1u) bits[s >> 5] |= 1u << (s & 31u);
+          }
+    }
+  }
   if (pos)
     HIP_TRY(hipMemcpy(pos, c->d_pos + g.pos_off + j * g.N, sizeof(uint32_t) * g.N,
                       hipMemcpyDeviceToHost));

@@ -33,16 +33,8 @@ namespace muca {
 
 namespace {
 
-constexpr uint32_t kCoordBits = 10;  // packed coordinates x | y << 10 | z << 20
-constexpr uint32_t kCoordMask = (1u << kCoordBits) - 1u;
-
 __device__ __forceinline__ uint32_t pack_coords(const GroupDesc& g, uint32_t s) {
-  const uint32_t q = div_L(s, g.L, g.invL);
-  const uint32_t x = s - q * (uint32_t)g.L;
-  if (g.d == 2) return x | (q << kCoordBits);
-  const uint32_t z = div_L(q, g.L, g.invL);
-  const uint32_t y = q - z * (uint32_t)g.L;
-  return x | (y << kCoordBits) | (z << (2 * kCoordBits));
+  return site_xyz(g, s);
 }
 
 template <bool kLds>
@@ -57,47 +49,79 @@ __device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
   else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Word and bit of a site: linear in LDS; in device memory the group's layout
+// (linear or bricked, see bit_ref).
 template <bool kLds>
-__device__ __forceinline__ void flip(uint32_t* bits, uint32_t so, uint32_t sn) {
+__device__ __forceinline__ BitRef locate(const GroupDesc& g, uint32_t s, uint32_t xyz) {
+  if constexpr (kLds) return BitRef{s >> 5, s & 31u};
+  else return bit_ref(g, s, xyz);
+}
+
+template <bool kLds>
+__device__ __forceinline__ void flip(const GroupDesc& g, uint32_t* bits, uint32_t so,
+                                     uint32_t sox, uint32_t sn, uint32_t snx) {
+  const BitRef a = locate<kLds>(g, so, sox), b = locate<kLds>(g, sn, snx);
   if constexpr (kLds) {
-    atomicAnd(&bits[so >> 5], ~(1u << (so & 31u)));
-    atomicOr(&bits[sn >> 5], 1u << (sn & 31u));
+    atomicAnd(&bits[a.word], ~(1u << a.bit));
+    atomicOr(&bits[b.word], 1u << b.bit);
   } else {
-    __hip_atomic_fetch_and(&bits[so >> 5], ~(1u << (so & 31u)), __ATOMIC_RELAXED,
+    __hip_atomic_fetch_and(&bits[a.word], ~(1u << a.bit), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_or(&bits[sn >> 5], 1u << (sn & 31u), __ATOMIC_RELAXED,
+    __hip_atomic_fetch_or(&bits[b.word], 1u << b.bit, __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+}
+
+// Word i (0..3) of a Philox block, as two selects (no indexed array).
+__device__ __forceinline__ uint32_t pick4(const U4& q, int i) {
+  const uint32_t lo = (i & 1) ? q.y : q.x;
+  const uint32_t hi = (i & 1) ? q.w : q.z;
+  return (i & 2) ? hi : lo;
 }
 
 // Per-lane constants of one neighbour role: coordinate field, edge value,
 // step and wrapped step along the lane's axis and direction.
 struct NbrRole {
   uint32_t shift, edge;
-  int32_t step, wrap;
+  int32_t step, wrap;    // of the linear index
+  uint32_t cstep, cwrap;  // of the packed coordinates (mod 2^32)
 };
 
 __device__ __forceinline__ NbrRole make_role(const GroupDesc& g, int dir) {
-  NbrRole r{0u, 0xFFFFFFFFu, 0, 0};  // dir < 0: the site itself
+  NbrRole r{0u, 0xFFFFFFFFu, 0, 0, 0u, 0u};  // dir < 0: the site itself
   if (dir < 0) return r;
   const int axis = dir >> 1;
   const int32_t stride = axis == 0 ? 1 : (axis == 1 ? g.L : g.LL);
-  r.shift = kCoordBits * (uint32_t)axis;
+  r.shift = kXyzBits * (uint32_t)axis;
+  const uint32_t unit = 1u << r.shift;
   if ((dir & 1) == 0) {
     r.edge = (uint32_t)(g.L - 1);
     r.step = stride;
     r.wrap = -(g.L - 1) * stride;
+    r.cstep = unit;
+    r.cwrap = 0u - (uint32_t)(g.L - 1) * unit;
   } else {
     r.edge = 0u;
     r.step = -stride;
     r.wrap = (g.L - 1) * stride;
+    r.cstep = 0u - unit;
+    r.cwrap = (uint32_t)(g.L - 1) * unit;
   }
   return r;
 }
 
-__device__ __forceinline__ uint32_t role_site(const NbrRole& r, uint32_t lin, uint32_t xyz) {
-  const uint32_t c = (xyz >> r.shift) & kCoordMask;
-  return lin + (uint32_t)((c == r.edge) ? r.wrap : r.step);
+// Linear index and bit location of the role's site.
+template <bool kLds>
+__device__ __forceinline__ uint32_t role_locate(const GroupDesc& g, const NbrRole& r,
+                                                uint32_t lin, uint32_t xyz, BitRef& at) {
+  const bool edge = ((xyz >> r.shift) & kXyzMask) == r.edge;
+  const uint32_t s = lin + (uint32_t)(edge ? r.wrap : r.step);
+  if constexpr (kLds) {
+    at = BitRef{s >> 5, s & 31u};
+  } else {
+    at = bit_ref(g, s, xyz + (edge ? r.cwrap : r.cstep));
+  }
+  return s;
 }
 
 template <int G>
@@ -107,9 +131,10 @@ __device__ __forceinline__ uint32_t sub_mask(uint64_t ballot, int base) {
 }
 
 // Broadcast lane A (compile-time) of each 16-lane row, or lane a of the wave.
+// Every lane of every row is written, so no old value is needed.
 template <int A>
 __device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + A, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + A, 0xF, 0xF, true);
 }
 
 // Walker state and per-lane constants of one cooperative walker.
@@ -122,15 +147,18 @@ struct Walker {
   const uint32_t* th;  // threshold table (LDS copy or device memory)
   int32_t* hist;
   int ls, base, d2, nd;
-  uint32_t V, N, key0, seed32, in_sweep;
+  uint32_t V, N, key0, seed32;
   int32_t E;
   uint64_t t;
   uint32_t Trow;
   // lane roles of the main gather: [0,2d) nbr(s_o), 2d: c2, 2d+1: c3,
   // [2d+2, 4d+2) nbr(c2) and, when 6d+2 lanes are available (full), also
-  // [4d+2, 6d+2) nbr(c3)
+  // [4d+2, 6d+2) nbr(c3).  With state in device memory the gather is bound
+  // by line fetches, so c3 and its neighbours (needed only when c2 is
+  // occupied, probability ~rho) are not read speculatively: lane 2d+1 reads
+  // c2's word again and c3 is read in the rare path.
   NbrRole role;
-  bool role_on, role_so, role_c3, full;
+  bool role_so, role_c3, full;
   NbrRole role2;  // lanes [0, 2d): nbr of s_n in the second gather
   // batch values of lane ls (attempt t + ls)
   uint32_t b_k, b_u, b_c2, b_c2x, b_c3, b_c3x, b_so, b_sox;
@@ -163,20 +191,27 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   // main gather
   const uint32_t blin = W.role_so ? so : (W.role_c3 ? c3 : c2);
   const uint32_t bxyz = W.role_so ? sox : (W.role_c3 ? c3x : c2x);
-  const uint32_t site = role_site(W.role, blin, bxyz);
-  uint32_t v = 0;
-  if (W.role_on) v = ld<kLds>(&W.bits[site >> 5]);
-  const bool occ = W.role_on && ((v >> (site & 31u)) & 1u);
-  const bool isso = W.role_on && (site == so);
-  const uint32_t m = sub_mask<G>(__ballot(occ), W.base);
-  const uint32_t nm = m & ~sub_mask<G>(__ballot(isso), W.base);  // occupied, not s_o
+  BitRef at;
+  const uint32_t site = role_locate<kLds>(g, W.role, blin, bxyz, at);
+  // Every lane loads (a lane without a role reads its base site, a valid
+  // word) and the masks below only look at bits of lanes with roles, so the
+  // ballots need no lane predicate.  Bits above the walker's 16 may belong
+  // to the next walker of the wave; every use below selects its own bits.
+  const uint32_t v = ld<kLds>(&W.bits[at.word]);
+  const uint32_t m = (uint32_t)(__ballot(((v >> at.bit) & 1u) != 0u) >> W.base);
+  const uint32_t nm = m & ~(uint32_t)(__ballot(site == so) >> W.base);  // occupied, not s_o
   const int ko = __popc(m & dmask);
   const bool c2free = !((m >> d2) & 1u);
-  const bool c3free = !((m >> (d2 + 1)) & 1u);
+  bool c3free = !((m >> (d2 + 1)) & 1u);  // LDS state only (speculative c3)
   uint32_t sn = c2free ? c2 : c3;
   uint32_t snx = c2free ? c2x : c3x;
   int kn = __popc((nm >> (c2free ? d2 + 2 : 2 * d2 + 2)) & dmask);
   if (!c2free && !(W.full && c3free)) {
+    if constexpr (!kLds) {
+      const BitRef a3 = locate<kLds>(g, c3, c3x);
+      const uint32_t w3 = ld<kLds>(&W.bits[a3.word]);
+      c3free = !((w3 >> a3.bit) & 1u);
+    }
     if (!c3free) {
       // both candidates occupied: words 0..3 of blocks 1, 2, ... in order
       uint32_t blk = 0;
@@ -184,37 +219,40 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
         blk += 1;
         const U4 q = philox((uint32_t)ta, (uint32_t)(ta >> 32), blk, 0u, W.key0, W.seed32);
         const int l4 = W.ls & 3;
-        const uint32_t word = (l4 == 0) ? q.x : (l4 == 1) ? q.y : (l4 == 2) ? q.z : q.w;
+        const uint32_t word = pick4(q, l4);
         const uint32_t cand = draw(word, W.V);
         uint32_t vv = 0;
-        if (W.ls < 4) vv = ld<kLds>(&W.bits[cand >> 5]);
-        const bool fr = (W.ls < 4) && !((vv >> (cand & 31u)) & 1u);
+        BitRef ac{cand >> 5, cand & 31u};
+        if constexpr (!kLds) ac = bit_of(g, cand);
+        if (W.ls < 4) vv = ld<kLds>(&W.bits[ac.word]);
+        const bool fr = (W.ls < 4) && !((vv >> ac.bit) & 1u);
         const uint32_t fm = sub_mask<G>(__ballot(fr), W.base) & 0xFu;
         if (fm) {
           const int first = __ffs(fm) - 1;
-          const uint32_t pick = first == 0 ? q.x : first == 1 ? q.y : first == 2 ? q.z : q.w;
-          sn = draw(pick, W.V);
+          sn = draw(pick4(q, first), W.V);
           snx = pack_coords(g, sn);
           break;
         }
       }
     }
     // second gather: neighbours of s_n, not counting s_o
-    const uint32_t s3 = role_site(W.role2, sn, snx);
+    BitRef at3;
+    const uint32_t s3 = role_locate<kLds>(g, W.role2, sn, snx, at3);
     uint32_t v3 = 0;
     const bool on3 = W.ls < d2;
-    if (on3) v3 = ld<kLds>(&W.bits[s3 >> 5]);
-    const bool occ3 = on3 && ((v3 >> (s3 & 31u)) & 1u) && (s3 != so);
+    if (on3) v3 = ld<kLds>(&W.bits[at3.word]);
+    const bool occ3 = on3 && ((v3 >> at3.bit) & 1u) && (s3 != so);
     kn = __popc(sub_mask<G>(__ballot(occ3), W.base));
   }
   const int dE = ko - kn;
-  // every lane of the threshold row tests u; the entry of dE decides
-  const bool ok = (W.ls < W.nd) && accepts(W.Trow, u);
-  const bool acc = (sub_mask<G>(__ballot(ok), W.base) >> (dE + d2)) & 1u;
+  // every lane of the threshold row tests u (accepts(): T = kAlways or u < T;
+  // lanes past the row hold 0, never); the entry of dE decides
+  const uint64_t ok = __ballot(u < W.Trow) | __ballot(W.Trow == kAlways);
+  const bool acc = (ok >> (W.base + dE + d2)) & 1u;
   if (acc && W.ls == 0) {
     st<kLds>(&W.plin[k], sn);
     if constexpr (kLds) W.pxyz[k] = snx;
-    flip<kLds>(W.bits, so, sn);
+    flip<kLds>(g, W.bits, so, sox, sn, snx);
   }
   if constexpr (!kLds) {
     if (acc) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -224,11 +262,9 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   W.b_so = take ? sn : W.b_so;
   W.b_sox = take ? snx : W.b_sox;
   W.E += acc ? dE : 0;
-  if (acc && dE != 0 && W.ls < W.nd) W.Trow = W.th[(W.E - g.e_lo) * W.nd + W.ls];
-  W.in_sweep += 1;
-  const bool sweep_end = W.in_sweep == W.V;
-  if (sweep_end && W.ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
-  W.in_sweep = sweep_end ? 0u : W.in_sweep;
+  // (E - e_lo) < 2^24 and nd <= 13: a full-rate 24-bit product
+  if (acc && dE != 0 && W.ls < W.nd)
+    W.Trow = W.th[__umul24((uint32_t)(W.E - g.e_lo), (uint32_t)W.nd) + (uint32_t)W.ls];
 }
 
 template <int A, int G, bool kLds, bool kTbl>
@@ -251,7 +287,7 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
     uint64_t* __restrict__ gT, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
     const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
-    int tbl_words, int hist_words) {
+    int tbl_words, int hist_words, int spread) {
   static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
   // LDS: [threshold table (tbl_words)] [block histogram (hist_words, LDS-state mode)]
   //      [walker slots]
@@ -263,8 +299,11 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   W.g = &g;
   W.ls = threadIdx.x & (G - 1);
   W.base = (threadIdx.x & 63) & ~(G - 1);
-  const int slot = threadIdx.x / G;
-  const bool has = slot < task.count;
+  // spread > 1 (16 lanes per walker only): a walker in every spread-th row,
+  // the other rows idle, so that a small population fills more wavefronts
+  const int row = threadIdx.x / G;
+  const int slot = row / spread;
+  const bool has = (row % spread) == 0 && slot < task.count;
   const int w = task.first + slot;
   const int64_t j = w - g.first_walker;
   W.d2 = 2 * g.d;
@@ -304,11 +343,10 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   if (has) {
     const int d2 = W.d2;
     const int ls = W.ls;
-    W.full = 3 * d2 + 2 <= G;
+    W.full = kLds && 3 * d2 + 2 <= G;
     const int nroles = W.full ? 3 * d2 + 2 : 2 * d2 + 2;
-    W.role_on = ls < nroles;
     W.role_so = ls < d2;
-    W.role_c3 = (ls == d2 + 1) || (ls >= 2 * d2 + 2 && ls < nroles);
+    W.role_c3 = kLds && ((ls == d2 + 1) || (ls >= 2 * d2 + 2 && ls < nroles));
     int dir = -1;
     if (ls < d2) dir = ls;
     else if (ls >= d2 + 2 && ls < 2 * d2 + 2) dir = ls - d2 - 2;
@@ -324,10 +362,12 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     W.E = gE[w];
     W.t = gT[w];
     W.Trow = (ls < W.nd) ? W.th[(W.E - g.e_lo) * W.nd + ls] : 0u;
-    W.in_sweep = 0;
-    const int64_t total = (int64_t)sweeps * (int64_t)W.V;
-    for (int64_t done = 0; done < total; done += G) {
-      const int nb = (int)((total - done) < G ? (total - done) : G);
+    // A batch never straddles the end of a sweep (the last batch of a sweep
+    // may be short; its spare lanes compute attempts that the next batch
+    // redoes), so the histogram entry is taken after the batch.
+    for (int sw = 0; sw < sweeps; ++sw) {
+    for (uint32_t done = 0; done < W.V; done += G) {
+      const int nb = (int)((W.V - done) < (uint32_t)G ? (W.V - done) : (uint32_t)G);
       batch_phase<G, kLds>(W);
       if constexpr (G == 16) {
         unrolled16<0, G, kLds, kTbl>(W, nb);
@@ -344,6 +384,8 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
         }
       }
       W.t += (uint64_t)nb;
+    }
+    if (ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
     }
     if (ls == 0) {
       gE[w] = W.E;
@@ -364,27 +406,27 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
 
 template __global__ void k_sweep_sub<16, true, true>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, true, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, true>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, true, true>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, true, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, false, true>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, false, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int);
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 
 }  // namespace muca

@@ -21,8 +21,8 @@ def converge(groups, seed, sweeps, max_iters, rule=M.MUCA_RULE_BERG, lnW0=None, 
              stream=None, chunk=0, progress=None, max_seconds=None):
     """Run the iteration until every group is flat (at most max_iters).
     chunk > 0 splits the run into resumed calls of `chunk` iterations (same
-    result), calls progress(done_iterations, flat_flags, seconds) after each
-    and stops early once max_seconds have passed (status not converged).
+    result), calls progress(done_iterations, flat_flags, seconds, detail)
+    after each (detail: flat_detail of the last histogram) and stops early once max_seconds have passed (status not converged).
     Returns a dict with the context, weights, histogram, per-group
     iterations, flags, status and wall time."""
     ctx = M.Context(groups, seed)
@@ -43,7 +43,7 @@ def converge(groups, seed, sweeps, max_iters, rule=M.MUCA_RULE_BERG, lnW0=None, 
                                   resume=done > 0)
         done += n
         if progress:
-            progress(done, flat, time.perf_counter() - t0)
+            progress(done, flat, time.perf_counter() - t0, flat_detail(ctx, H))
         if rc == M.MUCA_OK or done >= max_iters:
             break
         if max_seconds is not None and time.perf_counter() - t0 > max_seconds:
@@ -51,6 +51,24 @@ def converge(groups, seed, sweeps, max_iters, rule=M.MUCA_RULE_BERG, lnW0=None, 
     torch.cuda.synchronize()
     return {"ctx": ctx, "lnW": lnW, "H": H, "iters": iters, "flat": flat,
             "status": rc, "seconds": time.perf_counter() - t0}
+
+
+def flat_detail(ctx, H):
+    """Per group, for progress reports: (window bottom visited, window top
+    visited, min/max of H over visited bins, lowest visited energy, fraction
+    of the window's bins visited) of a histogram."""
+    h = H.cpu().numpy()
+    out = []
+    for g in range(ctx.ngroups):
+        lo, hi, off = ctx.window(g)
+        hg = h[off:off + hi - lo + 1]
+        seen = hg > 0
+        if not seen.any():
+            out.append((False, False, 0.0, None, 0.0))
+            continue
+        out.append((bool(seen[0]), bool(seen[-1]), round(float(hg[seen].min() / hg[seen].max()), 3),
+                    int(lo + np.argmax(seen)), round(float(seen.mean()), 4)))
+    return out
 
 
 def table_rows(ctx, lnW, groups=None):
@@ -120,31 +138,40 @@ def production(run, sweeps):
 
 
 def compare(net, groups, seed, sweeps, max_iters, layout=None, prod_sweeps=0, chunk=0,
-            progress=None, max_seconds=None):
-    """Iteration from flat weights vs from the network's proposal.  With
-    prod_sweeps > 0 the ln Omega estimates come from a production run with
-    each arm's converged weights, else from the last histogram."""
-    t0 = time.perf_counter()
-    probe = M.Context(groups, seed)
-    lnW0 = predict(net, probe)
-    probe.close()
-    infer_s = time.perf_counter() - t0
-    learned = converge(groups, seed, sweeps, max_iters, lnW0=lnW0, layout=layout, chunk=chunk,
-                       progress=(lambda *a: progress("learned", *a)) if progress else None,
+            progress=None, max_seconds=None, arms=("learned", "plain")):
+    """Iteration from the network's proposal ("learned") and from flat weights
+    ("plain"), same seeds and schedule.  With prod_sweeps > 0 the ln Omega
+    estimates come from a production run with each arm's final weights, else
+    from the last histogram; their largest difference (after removing the
+    mean offset, over bins both arms visited) is reported when both ran."""
+    runs = {}
+    for arm in arms:
+        t0 = time.perf_counter()
+        lnW0 = None
+        if arm == "learned":
+            probe = M.Context(groups, seed)
+            lnW0 = predict(net, probe)
+            probe.close()
+        infer_s = time.perf_counter() - t0  # the learned arm includes the network's inference
+        run = converge(groups, seed, sweeps, max_iters, lnW0=lnW0, layout=layout, chunk=chunk,
+                       progress=(lambda *a, _arm=arm: progress(_arm, *a)) if progress else None,
                        max_seconds=max_seconds)
-    learned["seconds"] += infer_s  # the learned arm includes the network's inference
-    plain = converge(groups, seed, sweeps, max_iters, layout=layout, chunk=chunk,
-                     progress=(lambda *a: progress("plain", *a)) if progress else None,
-                     max_seconds=max_seconds)
-    Hp = production(plain, prod_sweeps) if prod_sweeps else plain["H"]
-    Hl = production(learned, prod_sweeps) if prod_sweeps else learned["H"]
-    lo_p = ln_omega(plain["ctx"], plain["lnW"], Hp)
-    lo_l = ln_omega(learned["ctx"], learned["lnW"], Hl)
-    diffs = []
-    for a, b in zip(lo_p, lo_l):
-        both = ~np.isnan(a) & ~np.isnan(b)
-        d = a[both] - b[both]
-        diffs.append(float(np.max(np.abs(d - d.mean()))) if both.any() else float("nan"))
-    return {"plain": {k: plain[k] for k in ("iters", "flat", "status", "seconds")},
-            "learned": {k: learned[k] for k in ("iters", "flat", "status", "seconds")},
-            "ln_omega_max_abs_diff": diffs}
+        run["seconds"] += infer_s
+        runs[arm] = run
+    out = {arm: {k: r[k] for k in ("iters", "flat", "status", "seconds")}
+           for arm, r in runs.items()}
+    if len(runs) == 2:
+        lo = []
+        for arm in arms:
+            r = runs[arm]
+            Hx = production(r, prod_sweeps) if prod_sweeps else r["H"]
+            lo.append(ln_omega(r["ctx"], r["lnW"], Hx))
+        diffs = []
+        for a, b in zip(*lo):
+            both = ~np.isnan(a) & ~np.isnan(b)
+            d = a[both] - b[both]
+            diffs.append(float(np.max(np.abs(d - d.mean()))) if both.any() else float("nan"))
+        out["ln_omega_max_abs_diff"] = diffs
+    for r in runs.values():
+        r["ctx"].close()
+    return out

@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=5)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--stage", choices=("all", "train", "eval"), default="all")
+    ap.add_argument("--arms", default="learned,plain", help="arms of the comparison, in order")
     ap.add_argument("--net", default=None, help="parameter file (.npy) to save or load")
     ap.add_argument("--max-seconds", type=float, default=None,
                     help="wall-time budget of each iteration run (stops between chunks)")
@@ -78,8 +79,9 @@ def train_stage(args, out):
         log(f"train table {name}: groups {wl['groups']} sweeps {wl['sweeps']}")
         run = LR.converge(wl["groups"], wl["seed"], wl["sweeps"], args.train_max_iters,
                           chunk=args.chunk, max_seconds=args.max_seconds,
-                          progress=lambda n, f, s, nm=name: log(f"  {nm}: {n} iterations, "
-                                                                f"flat {list(f)}, {s:.1f} s"))
+                          progress=lambda n, f, s, d, nm=name: log(
+                              f"  {nm}: {n} iterations, flat {list(f)}, {s:.1f} s, "
+                              f"(bottom, top visited, min/max, lowest E, visited) {d}"))
         done = [g for g, f in enumerate(run["flat"]) if f]
         out["train"].append({"workload": name, "groups": [list(g) for g in wl["groups"]],
                              "sweeps": wl["sweeps"], "iters": list(run["iters"]),
@@ -107,11 +109,17 @@ def eval_stage(args, net, out):
     out["target_groups"] = [list(g) for g in wl["groups"]]
     out["target_sweeps"] = wl["sweeps"]
     log(f"target {args.target}: groups {wl['groups']} sweeps {wl['sweeps']}")
+    history = out.setdefault("history", {})
+
+    def progress(arm, n, f, s, d):
+        history.setdefault(arm, []).append({"iters": n, "seconds": round(s, 1), "detail": d})
+        log(f"  {arm}: {n} iterations, flat {list(f)}, {s:.1f} s, "
+            f"(bottom, top visited, min/max, lowest E, visited) {d}")
+
     res = LR.compare(net, wl["groups"], wl["seed"], wl["sweeps"], args.target_max_iters,
                      prod_sweeps=args.prod_sweeps, chunk=args.chunk,
-                     max_seconds=args.max_seconds,
-                     progress=lambda arm, n, f, s: log(f"  {arm}: {n} iterations, flat {list(f)}, "
-                                                       f"{s:.1f} s"))
+                     max_seconds=args.max_seconds, arms=tuple(args.arms.split(",")),
+                     progress=progress)
     out.update(res)
 
 

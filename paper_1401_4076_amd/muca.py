@@ -29,7 +29,11 @@ MUCA_LAYOUT_LANE = 1
 MUCA_LAYOUT_SUB16 = 2
 MUCA_LAYOUT_SUB64 = 3
 MUCA_LAYOUT_LOOK4 = 4
-LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64, MUCA_LAYOUT_LOOK4)
+MUCA_LAYOUT_SUB16X2 = 5
+MUCA_LAYOUT_SUB16X1 = 6
+MUCA_NUM_LAYOUTS = 7
+LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64, MUCA_LAYOUT_LOOK4,
+           MUCA_LAYOUT_SUB16X2, MUCA_LAYOUT_SUB16X1)
 
 # C ABI: name -> (restype, argtypes)
 _P = ctypes.POINTER
@@ -188,7 +192,7 @@ class Context:
     def autotune(self, lnW, probe_sweeps=1, stream=None):
         """Returns (chosen layout, [ms per layout index 0..4])."""
         ch = ctypes.c_int()
-        ms = (ctypes.c_double * 5)()
+        ms = (ctypes.c_double * MUCA_NUM_LAYOUTS)()
         _check(lib().mucaAutotune(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
                                   int(probe_sweeps), ctypes.byref(ch), ms, _stream(stream)))
         return ch.value, list(ms)

@@ -48,6 +48,7 @@ def _init_rc(groups, n=None, out=True):
     (1, 8, 4, 1, 0, 0), (4, 8, 4, 1, 0, 0), (2, 2, 2, 1, 0, 0), (2, 2000, 4, 1, 0, 0),
     (3, 300, 4, 1, 0, 0), (2, 8, 0, 1, 0, 0), (2, 8, 64, 1, 0, 0), (2, 8, 40, 1, 0, 0),
     (2, 8, 4, 0, 0, 0), (2, 8, 4, 1, -9, 0), (2, 8, 4, 1, -2, 1), (2, 8, 4, 1, -1, -2),
+    (3, 256, 6_000_000, 1, -(1 << 24), 0),  # 2^24 + 1 bins
 ])
 def test_invalid_groups_rejected_on_host(g):
     assert _init_rc([g]) == M.MUCA_EINVAL

@@ -63,6 +63,16 @@ def test_initial_placement_matches_oracle():
     assert_walkers_equal(ctx, ref, range(ctx.nwalkers))
 
 
+def test_bricked_placement_matches_oracle():
+    # 3D groups whose 16-walker state exceeds 160 KiB keep 8x8x8-bricked bits;
+    # mucaReadWalker returns the linear layout
+    groups = [(3, 16, 1300, 3), (3, 24, 1100, 2), (3, 16, 205, 2)]
+    say("bricked placement", groups)
+    ctx = M.Context(groups, seed=5)
+    ref = O.RefContext(groups, seed=5)
+    assert_walkers_equal(ctx, ref, range(ctx.nwalkers))
+
+
 def test_first_id_offsets_streams():
     say("first_id")
     ctx = M.Context([(2, 8, 16, 4)], seed=3, first_id=1000)
@@ -148,9 +158,10 @@ def test_flatness_matches_oracle():
 VARIANTS = [(M.MUCA_LAYOUT_LANE, 163840), (M.MUCA_LAYOUT_SUB16, 163840),
             (M.MUCA_LAYOUT_SUB16, 0), (M.MUCA_LAYOUT_SUB64, 163840), (M.MUCA_LAYOUT_SUB64, 0),
             (M.MUCA_LAYOUT_SUB16, 24576), (M.MUCA_LAYOUT_LOOK4, 163840),
-            (M.MUCA_LAYOUT_LOOK4, 24576)]
+            (M.MUCA_LAYOUT_LOOK4, 24576), (M.MUCA_LAYOUT_SUB16X2, 163840),
+            (M.MUCA_LAYOUT_SUB16X2, 0), (M.MUCA_LAYOUT_SUB16X1, 163840)]
 VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm", "sub16-lds24k",
-               "look4", "look4-lds24k"]
+               "look4", "look4-lds24k", "sub16x2-lds", "sub16x2-hbm", "sub16x1-lds"]
 
 
 def make_ctx(groups, seed, variant=None, first_id=0):
@@ -168,6 +179,10 @@ def make_ctx(groups, seed, variant=None, first_id=0):
     ([(3, 3, 5, 10), (3, 16, 205, 3)], 3),
     ([(2, 9, 20, 5, -30, -2)], 11),
     ([(2, 4, 8, 17, -12, 0), (3, 4, 30, 6, -80, 0)], 9),   # dense: many rejected candidates
+    # bricked occupation bits (3D, L % 8 == 0, state too large for LDS) beside a
+    # linear group; L = 24 has an odd number of bricks per axis
+    ([(3, 16, 1300, 3), (2, 8, 16, 2)], 2),
+    ([(3, 24, 1100, 2)], 1),
 ])
 def test_sweep_matches_oracle(groups, sweeps, variant):
     say("sweep", groups, sweeps, variant)
