@@ -63,7 +63,8 @@ def measured_traffic(workload, kernel_layout):
                    for n in ("muca_sweep_sub.hip", "muca_device.h"))
     if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
         return None
-    want = {2: "k_sweep_sub<16", 3: "k_sweep_sub<64"}.get(kernel_layout)
+    want = {2: "k_sweep_sub<16", 3: "k_sweep_sub<64", 5: "k_sweep_sub<16",
+            6: "k_sweep_sub<16"}.get(kernel_layout)
     if want is None or want not in rec["kernel"]:
         return None
     return rec["traffic_bytes_per_launch"]

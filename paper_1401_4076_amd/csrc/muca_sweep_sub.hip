@@ -23,8 +23,12 @@
 //
 // kLds: walker state (occupation bits, particle sites and their packed
 // coordinates) lives in LDS for the whole launch; otherwise occupation bits
-// and sites stay in device memory (workgroup-coherent accesses) and the
-// coordinates of s_o are recomputed in the batch phase.
+// and sites stay in device memory (workgroup-coherent accesses, the group's
+// bit layout: linear or bricked, see bit_ref) and the coordinates of s_o are
+// recomputed in the batch phase.  kPipe (device memory only): the gather of
+// the next attempt is issued before the current one is decided.
+// spread (16 lanes only): walkers sit in every spread-th 16-lane row, so a
+// small population fills more wavefronts (layouts SUB16X2, SUB16X1).
 #include "muca_kernels.h"
 
 #pragma clang fp contract(off)
@@ -32,10 +36,6 @@
 namespace muca {
 
 namespace {
-
-__device__ __forceinline__ uint32_t pack_coords(const GroupDesc& g, uint32_t s) {
-  return site_xyz(g, s);
-}
 
 template <bool kLds>
 __device__ __forceinline__ uint32_t ld(const uint32_t* p) {
@@ -137,6 +137,14 @@ __device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + A, 0xF, 0xF, true);
 }
 
+// One attempt's broadcast values, this lane's gather site, the site's bit in
+// the loaded word, and the word (pipelined device-memory path).
+struct Pend {
+  uint32_t k, u, c2, c2x, c3, c3x, so, sox, site, sh, v;
+};
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;  // no particle index or site (V <= 2^24)
+
 // Walker state and per-lane constants of one cooperative walker.
 template <int G, bool kLds, bool kTbl>
 struct Walker {
@@ -162,44 +170,51 @@ struct Walker {
   NbrRole role2;  // lanes [0, 2d): nbr of s_n in the second gather
   // batch values of lane ls (attempt t + ls)
   uint32_t b_k, b_u, b_c2, b_c2x, b_c3, b_c3x, b_so, b_sox;
+  // device-memory path: the previous attempt's move (particle, old and new
+  // site; kNone if rejected) and the fetch of the next batch's first attempt
+  uint32_t pm_k, pm_so, pm_sn, pm_snx;
+  Pend next;
 };
 
 template <int G, bool kLds, bool kTbl>
-__device__ __forceinline__ void batch_phase(Walker<G, kLds, kTbl>& W) {
+__device__ __forceinline__ void batch_phase(Walker<G, kLds, kTbl>& W, uint64_t t0) {
   const GroupDesc& g = *W.g;
-  const uint64_t tl = W.t + (uint64_t)W.ls;
+  const uint64_t tl = t0 + (uint64_t)W.ls;
   const U4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), 0u, 0u, W.key0, W.seed32);
   W.b_k = draw(r.x, W.N);
   W.b_u = r.y;
   W.b_c2 = draw(r.z, W.V);
   W.b_c3 = draw(r.w, W.V);
-  W.b_c2x = pack_coords(g, W.b_c2);
-  W.b_c3x = pack_coords(g, W.b_c3);
+  W.b_c2x = site_xyz(g, W.b_c2);
+  W.b_c3x = site_xyz(g, W.b_c3);
   W.b_so = ld<kLds>(&W.plin[W.b_k]);
   if constexpr (kLds) W.b_sox = W.pxyz[W.b_k];
-  else W.b_sox = pack_coords(g, W.b_so);
+  else W.b_sox = site_xyz(g, W.b_so);
 }
 
-// One attempt with the broadcast values of attempt ta.
+// This lane's site in the main gather of an attempt and its bit location.
+// (Plain values, not a struct reference: a select between fields of one
+// struct can be turned into an indexed stack load.)
 template <int G, bool kLds, bool kTbl>
-__device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, uint32_t u,
+__device__ __forceinline__ uint32_t gather_site(const Walker<G, kLds, kTbl>& W, uint32_t so,
+                                                uint32_t sox, uint32_t c2, uint32_t c2x,
+                                                uint32_t c3, uint32_t c3x, BitRef& at) {
+  const uint32_t blin = W.role_so ? so : (W.role_c3 ? c3 : c2);
+  const uint32_t bxyz = W.role_so ? sox : (W.role_c3 ? c3x : c2x);
+  return role_locate<kLds>(*W.g, W.role, blin, bxyz, at);
+}
+
+// The decision of attempt ta from the occupancy masks of its main gather
+// (m: occupied role sites, nm: occupied and not s_o; bit i = role lane i of
+// the walker), then the move.
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, uint32_t u,
                                         uint32_t c2, uint32_t c2x, uint32_t c3, uint32_t c3x,
-                                        uint32_t so, uint32_t sox, uint64_t ta) {
+                                        uint32_t so, uint32_t sox, uint64_t ta, uint32_t m,
+                                        uint32_t nm, uint64_t ok) {
   const GroupDesc& g = *W.g;
   const int d2 = W.d2;
   const uint32_t dmask = (1u << d2) - 1u;
-  // main gather
-  const uint32_t blin = W.role_so ? so : (W.role_c3 ? c3 : c2);
-  const uint32_t bxyz = W.role_so ? sox : (W.role_c3 ? c3x : c2x);
-  BitRef at;
-  const uint32_t site = role_locate<kLds>(g, W.role, blin, bxyz, at);
-  // Every lane loads (a lane without a role reads its base site, a valid
-  // word) and the masks below only look at bits of lanes with roles, so the
-  // ballots need no lane predicate.  Bits above the walker's 16 may belong
-  // to the next walker of the wave; every use below selects its own bits.
-  const uint32_t v = ld<kLds>(&W.bits[at.word]);
-  const uint32_t m = (uint32_t)(__ballot(((v >> at.bit) & 1u) != 0u) >> W.base);
-  const uint32_t nm = m & ~(uint32_t)(__ballot(site == so) >> W.base);  // occupied, not s_o
   const int ko = __popc(m & dmask);
   const bool c2free = !((m >> d2) & 1u);
   bool c3free = !((m >> (d2 + 1)) & 1u);  // LDS state only (speculative c3)
@@ -230,7 +245,7 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
         if (fm) {
           const int first = __ffs(fm) - 1;
           sn = draw(pick4(q, first), W.V);
-          snx = pack_coords(g, sn);
+          snx = site_xyz(g, sn);
           break;
         }
       }
@@ -245,9 +260,6 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
     kn = __popc(sub_mask<G>(__ballot(occ3), W.base));
   }
   const int dE = ko - kn;
-  // every lane of the threshold row tests u (accepts(): T = kAlways or u < T;
-  // lanes past the row hold 0, never); the entry of dE decides
-  const uint64_t ok = __ballot(u < W.Trow) | __ballot(W.Trow == kAlways);
   const bool acc = (ok >> (W.base + dE + d2)) & 1u;
   if (acc && W.ls == 0) {
     st<kLds>(&W.plin[k], sn);
@@ -257,6 +269,12 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   if constexpr (!kLds) {
     if (acc) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   }
+  if constexpr (!kLds) {
+    W.pm_k = acc ? k : kNone;
+    W.pm_so = acc ? so : kNone;
+    W.pm_sn = acc ? sn : kNone;
+    W.pm_snx = snx;
+  }
   // later attempts of this batch that chose the same particle see its new site
   const bool take = acc && (W.b_k == k);
   W.b_so = take ? sn : W.b_so;
@@ -265,6 +283,107 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   // (E - e_lo) < 2^24 and nd <= 13: a full-rate 24-bit product
   if (acc && dE != 0 && W.ls < W.nd)
     W.Trow = W.th[__umul24((uint32_t)(W.E - g.e_lo), (uint32_t)W.nd) + (uint32_t)W.ls];
+}
+
+// One attempt with the broadcast values of attempt ta (state in LDS).
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, uint32_t u,
+                                        uint32_t c2, uint32_t c2x, uint32_t c3, uint32_t c3x,
+                                        uint32_t so, uint32_t sox, uint64_t ta) {
+  BitRef at;
+  const uint32_t site = gather_site(W, so, sox, c2, c2x, c3, c3x, at);
+  // Every lane loads (a lane without a role reads its base site, a valid
+  // word) and the masks only look at bits of lanes with roles, so the
+  // ballots need no lane predicate.  Bits above the walker's 16 may belong
+  // to the next walker of the wave; every use selects its own bits.
+  const uint32_t v = ld<kLds>(&W.bits[at.word]);
+  // while the gather is in flight: every lane of the threshold row tests u
+  // (accepts(): T = kAlways or u < T; lanes past the row hold 0, never); the
+  // entry of the attempt's dE decides
+  const uint64_t ok = __ballot(u < W.Trow) | __ballot(W.Trow == kAlways);
+  const uint32_t m = (uint32_t)(__ballot(((v >> at.bit) & 1u) != 0u) >> W.base);
+  const uint32_t nm = m & ~(uint32_t)(__ballot(site == so) >> W.base);  // occupied, not s_o
+  resolve<G, kLds, kTbl>(W, k, u, c2, c2x, c3, c3x, so, sox, ta, m, nm, ok);
+}
+
+// ---- device-memory state: the gather of attempt a + 1 is issued before
+// attempt a is decided, so its memory latency overlaps the decision.  When
+// a + 1 is decided, the gathered bits are corrected for a's move (s_o empty,
+// s_n occupied; either value of the word is corrected the same way), and if
+// that move displaced a + 1's particle, its neighbourhood is read again.
+// (With state in LDS the extra instructions cost more than the LDS latency
+// they hide, so that path decides each attempt after its own gather.)
+
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void gather(const Walker<G, kLds, kTbl>& W, Pend& p) {
+  BitRef at;
+  p.site = gather_site(W, p.so, p.sox, p.c2, p.c2x, p.c3, p.c3x, at);
+  p.sh = at.bit;
+  p.v = ld<kLds>(&W.bits[at.word]);
+}
+
+template <int A, int G, bool kLds, bool kTbl>
+__device__ __forceinline__ Pend fetch16(const Walker<G, kLds, kTbl>& W) {
+  Pend p;
+  p.k = row_bcast<A>(W.b_k);
+  p.u = row_bcast<A>(W.b_u);
+  p.c2 = row_bcast<A>(W.b_c2);
+  p.c2x = row_bcast<A>(W.b_c2x);
+  p.c3 = row_bcast<A>(W.b_c3);
+  p.c3x = row_bcast<A>(W.b_c3x);
+  p.so = row_bcast<A>(W.b_so);
+  p.sox = row_bcast<A>(W.b_sox);
+  gather(W, p);
+  return p;
+}
+
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ Pend fetch64(const Walker<G, kLds, kTbl>& W, int a) {
+  Pend p;
+  p.k = __builtin_amdgcn_readlane(W.b_k, a);
+  p.u = __builtin_amdgcn_readlane(W.b_u, a);
+  p.c2 = __builtin_amdgcn_readlane(W.b_c2, a);
+  p.c2x = __builtin_amdgcn_readlane(W.b_c2x, a);
+  p.c3 = __builtin_amdgcn_readlane(W.b_c3, a);
+  p.c3x = __builtin_amdgcn_readlane(W.b_c3x, a);
+  p.so = __builtin_amdgcn_readlane(W.b_so, a);
+  p.sox = __builtin_amdgcn_readlane(W.b_sox, a);
+  gather(W, p);
+  return p;
+}
+
+template <int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void decide(Walker<G, kLds, kTbl>& W, Pend p, uint64_t ta) {
+  const uint64_t ok = __ballot(p.u < W.Trow) | __ballot(W.Trow == kAlways);  // as in attempt()
+  uint32_t bit = (p.v >> p.sh) & 1u;
+  bit = (p.site == W.pm_sn) ? 1u : ((p.site == W.pm_so) ? 0u : bit);
+  const bool moved = p.k == W.pm_k;
+  if (__ballot(moved) != 0ull) {
+    p.so = moved ? W.pm_sn : p.so;
+    p.sox = moved ? W.pm_snx : p.sox;
+    BitRef at;
+    const uint32_t site = gather_site(W, p.so, p.sox, p.c2, p.c2x, p.c3, p.c3x, at);
+    const uint32_t v = ld<kLds>(&W.bits[at.word]);
+    bit = moved ? ((v >> at.bit) & 1u) : bit;
+    p.site = moved ? site : p.site;
+  }
+  const uint32_t m = (uint32_t)(__ballot(bit != 0u) >> W.base);
+  const uint32_t nm = m & ~(uint32_t)(__ballot(p.site == p.so) >> W.base);
+  resolve<G, kLds, kTbl>(W, p.k, p.u, p.c2, p.c2x, p.c3, p.c3x, p.so, p.sox, ta, m, nm, ok);
+}
+
+// Attempts A..nb-2 of a 16-lane batch; cur holds attempt A's fetch.  Returns
+// the fetch of the batch's last attempt, still undecided.
+template <int A, int G, bool kLds, bool kTbl>
+__device__ __forceinline__ Pend run16(Walker<G, kLds, kTbl>& W, Pend cur, int nb) {
+  if constexpr (A == 15) {
+    return cur;
+  } else {
+    if (A + 1 == nb) return cur;
+    const Pend nxt = fetch16<A + 1, G, kLds, kTbl>(W);
+    decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)A);
+    return run16<A + 1, G, kLds, kTbl>(W, nxt, nb);
+  }
 }
 
 template <int A, int G, bool kLds, bool kTbl>
@@ -281,7 +400,7 @@ __device__ __forceinline__ void unrolled16(Walker<G, kLds, kTbl>& W, int nb) {
 
 }  // namespace
 
-template <int G, bool kLds, bool kTbl>
+template <int G, bool kLds, bool kTbl, bool kPipe>
 __global__ void __launch_bounds__(256) k_sweep_sub(
     const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
@@ -289,6 +408,7 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
     int tbl_words, int hist_words, int spread) {
   static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
+  static_assert(!(kLds && kPipe), "the pipelined gather is for device-memory state");
   // LDS: [threshold table (tbl_words)] [block histogram (hist_words, LDS-state mode)]
   //      [walker slots]
   extern __shared__ uint32_t smem[];
@@ -330,7 +450,7 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
       for (int i = W.ls; i < g.N; i += G) {
         const uint32_t s = sp[i];
         W.plin[i] = s;
-        W.pxyz[i] = pack_coords(g, s);
+        W.pxyz[i] = site_xyz(g, s);
       }
     }
   } else {
@@ -365,27 +485,62 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     // A batch never straddles the end of a sweep (the last batch of a sweep
     // may be short; its spare lanes compute attempts that the next batch
     // redoes), so the histogram entry is taken after the batch.
-    for (int sw = 0; sw < sweeps; ++sw) {
-    for (uint32_t done = 0; done < W.V; done += G) {
-      const int nb = (int)((W.V - done) < (uint32_t)G ? (W.V - done) : (uint32_t)G);
-      batch_phase<G, kLds>(W);
-      if constexpr (G == 16) {
-        unrolled16<0, G, kLds, kTbl>(W, nb);
-      } else {
-        for (int a = 0; a < nb; ++a) {
-          attempt<G, kLds, kTbl>(W, __builtin_amdgcn_readlane(W.b_k, a),
-                           __builtin_amdgcn_readlane(W.b_u, a),
-                           __builtin_amdgcn_readlane(W.b_c2, a),
-                           __builtin_amdgcn_readlane(W.b_c2x, a),
-                           __builtin_amdgcn_readlane(W.b_c3, a),
-                           __builtin_amdgcn_readlane(W.b_c3x, a),
-                           __builtin_amdgcn_readlane(W.b_so, a),
-                           __builtin_amdgcn_readlane(W.b_sox, a), W.t + (uint64_t)a);
+    if constexpr (!kPipe) {
+      for (int sw = 0; sw < sweeps; ++sw) {
+        for (uint32_t done = 0; done < W.V; done += G) {
+          const int nb = (int)((W.V - done) < (uint32_t)G ? (W.V - done) : (uint32_t)G);
+          batch_phase<G, kLds>(W, W.t);
+          if constexpr (G == 16) {
+            unrolled16<0, G, kLds, kTbl>(W, nb);
+          } else {
+            for (int a = 0; a < nb; ++a) {
+              attempt<G, kLds, kTbl>(W, __builtin_amdgcn_readlane(W.b_k, a),
+                                     __builtin_amdgcn_readlane(W.b_u, a),
+                                     __builtin_amdgcn_readlane(W.b_c2, a),
+                                     __builtin_amdgcn_readlane(W.b_c2x, a),
+                                     __builtin_amdgcn_readlane(W.b_c3, a),
+                                     __builtin_amdgcn_readlane(W.b_c3x, a),
+                                     __builtin_amdgcn_readlane(W.b_so, a),
+                                     __builtin_amdgcn_readlane(W.b_sox, a),
+                                     W.t + (uint64_t)a);
+            }
+          }
+          W.t += (uint64_t)nb;
         }
+        if (ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
       }
-      W.t += (uint64_t)nb;
-    }
-    if (ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+    } else {
+      W.pm_k = W.pm_so = W.pm_sn = kNone;
+      W.pm_snx = 0u;
+      batch_phase<G, kLds>(W, W.t);
+      if constexpr (G == 16) W.next = fetch16<0, G, kLds, kTbl>(W);
+      else W.next = fetch64<G, kLds, kTbl>(W, 0);
+      for (int sw = 0; sw < sweeps; ++sw) {
+        for (uint32_t done = 0; done < W.V; done += G) {
+          const int nb = (int)((W.V - done) < (uint32_t)G ? (W.V - done) : (uint32_t)G);
+          const bool more = (done + (uint32_t)nb < W.V) || (sw + 1 < sweeps);
+          Pend cur;
+          if constexpr (G == 16) {
+            cur = run16<0, G, kLds, kTbl>(W, W.next, nb);
+          } else {
+            cur = W.next;
+            for (int a = 0; a + 1 < nb; ++a) {
+              const Pend nxt = fetch64<G, kLds, kTbl>(W, a + 1);
+              decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)a);
+              cur = nxt;
+            }
+          }
+          // the batch's last attempt; the next batch is fetched before it is decided
+          if (more) {
+            batch_phase<G, kLds>(W, W.t + (uint64_t)nb);
+            if constexpr (G == 16) W.next = fetch16<0, G, kLds, kTbl>(W);
+            else W.next = fetch64<G, kLds, kTbl>(W, 0);
+          }
+          decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)(nb - 1));
+          W.t += (uint64_t)nb;
+        }
+        if (ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+      }
     }
     if (ls == 0) {
       gE[w] = W.E;
@@ -404,28 +559,34 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   }
 }
 
-template __global__ void k_sweep_sub<16, true, true>(
+template __global__ void k_sweep_sub<16, true, true, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<16, true, false>(
+template __global__ void k_sweep_sub<16, true, false, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<16, false, true>(
+template __global__ void k_sweep_sub<16, false, true, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<16, false, false>(
+template __global__ void k_sweep_sub<16, false, false, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<64, true, true>(
+template __global__ void k_sweep_sub<16, false, true, true>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<64, true, false>(
+template __global__ void k_sweep_sub<16, false, false, true>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<64, false, true>(
+template __global__ void k_sweep_sub<64, true, true, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<64, false, false>(
+template __global__ void k_sweep_sub<64, true, false, false>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+template __global__ void k_sweep_sub<64, false, true, false>(
+    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
+    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+template __global__ void k_sweep_sub<64, false, false, false>(
     const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
     const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 
