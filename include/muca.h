@@ -66,8 +66,10 @@ extern "C" {
 #define MUCA_LAYOUT_LOOK4 4 /* one wavefront per walker, four attempts gathered per step
                                (walker state in LDS; else runs as SUB64) */
 #define MUCA_LAYOUT_SUB16X2 5 /* 16 lanes per walker, 2 walkers per wavefront (more
-                                 wavefronts per SIMD for small populations) */
-#define MUCA_LAYOUT_SUB16X1 6 /* 16 lanes per walker, 1 walker per wavefront */
+                                 wavefronts per SIMD for small populations); with
+                                 state in device memory the next attempt's gather
+                                 is issued before the current one is decided */
+#define MUCA_LAYOUT_SUB16X1 6 /* as SUB16X2 with 1 walker per wavefront */
 #define MUCA_NUM_LAYOUTS 7    /* layout indices 0 .. MUCA_NUM_LAYOUTS - 1 */
 
 typedef struct muca_context* muca_ctx;

@@ -28,17 +28,6 @@ namespace muca {
 
 namespace {
 
-constexpr uint32_t kCB = 10;  // packed coordinates x | y << 10 | z << 20
-constexpr uint32_t kCM = (1u << kCB) - 1u;
-
-__device__ __forceinline__ uint32_t pack_xyz(const GroupDesc& g, uint32_t s) {
-  const uint32_t q = div_L(s, g.L, g.invL);
-  const uint32_t x = s - q * (uint32_t)g.L;
-  if (g.d == 2) return x | (q << kCB);
-  const uint32_t z = div_L(q, g.L, g.invL);
-  return x | ((q - z * (uint32_t)g.L) << kCB) | (z << (2 * kCB));
-}
-
 struct Role {
   uint32_t shift, edge;
   int32_t step, wrap;
@@ -49,7 +38,7 @@ __device__ __forceinline__ Role role_of(const GroupDesc& g, int dir) {
   if (dir < 0) return r;
   const int axis = dir >> 1;
   const int32_t stride = axis == 0 ? 1 : (axis == 1 ? g.L : g.LL);
-  r.shift = kCB * (uint32_t)axis;
+  r.shift = kXyzBits * (uint32_t)axis;
   if ((dir & 1) == 0) {
     r.edge = (uint32_t)(g.L - 1);
     r.step = stride;
@@ -63,7 +52,7 @@ __device__ __forceinline__ Role role_of(const GroupDesc& g, int dir) {
 }
 
 __device__ __forceinline__ uint32_t at_role(const Role& r, uint32_t lin, uint32_t xyz) {
-  const uint32_t c = (xyz >> r.shift) & kCM;
+  const uint32_t c = (xyz >> r.shift) & kXyzMask;
   return lin + (uint32_t)((c == r.edge) ? r.wrap : r.step);
 }
 
@@ -180,7 +169,7 @@ __device__ __forceinline__ int exact_attempt(Look& W, uint32_t so, uint32_t sox,
         const int first = __ffs(fm) - 1;
         const uint32_t pick = first == 0 ? q.x : first == 1 ? q.y : first == 2 ? q.z : q.w;
         sn = draw(pick, W.V);
-        snx = pack_xyz(g, sn);
+        snx = site_xyz(g, sn);
         break;
       }
     }
@@ -204,8 +193,8 @@ __device__ __forceinline__ void batch(Look& W) {
   W.b_u = r.y;
   W.b_c2 = draw(r.z, W.V);
   W.b_c3 = draw(r.w, W.V);
-  W.b_c2x = pack_xyz(g, W.b_c2);
-  W.b_c3x = pack_xyz(g, W.b_c3);
+  W.b_c2x = site_xyz(g, W.b_c2);
+  W.b_c3x = site_xyz(g, W.b_c3);
   W.b_so = W.plin[W.b_k];
   W.b_sox = W.pxyz[W.b_k];
 }
@@ -324,7 +313,7 @@ __global__ void __launch_bounds__(256) k_sweep_look(
     for (int i = W.lane; i < g.N; i += 64) {
       const uint32_t s = sp[i];
       W.plin[i] = s;
-      W.pxyz[i] = pack_xyz(g, s);
+      W.pxyz[i] = site_xyz(g, s);
     }
   }
   __syncthreads();

@@ -289,9 +289,13 @@ def test_run_from_nonzero_weights():
     _run_both(groups, 8, 50, 3, lnW0=lnW0)
 
 
-def test_edge_single_particle_and_small_lattices():
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_edge_single_particle_and_small_lattices(variant):
+    # N = 1; V = 9 and 27 (sweeps shorter than a 16- or 64-attempt batch);
+    # N = V - 1 (every candidate but one occupied)
     groups = [(3, 5, 1, 3), (2, 3, 4, 2, -4, 0), (3, 3, 13, 2, -30, 0), (2, 4, 15, 2, -28, 0)]
-    ctx = M.Context(groups, seed=1)
+    say("edge", groups, variant)
+    ctx = make_ctx(groups, 1, variant)
     ref = O.RefContext(groups, seed=1)
     assert ctx.window(0)[:2] == (0, 0)
     lnW = W.random_lnW(ctx.total_bins, seed=4, scale=1.0)

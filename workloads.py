@@ -12,6 +12,9 @@ Workloads (synthetic lattice-gas states; the paper uses no dataset):
   batched_3d    8 groups L in {24,32} x rho in {.02,.04,.06,.10},
                 16384 walkers split in proportion to N, until flat, S=1e2
   large_3d      3D L=48, rho=0.03 (N=3318), 16384 walkers, until flat, S=1e2
+  held_out_3d   3D L=24, rho=0.03 (N=415), 4096 walkers, until flat, S=1e2: the
+                large lattice's density at a size both weight arms can flatten
+                within minutes (a held-out target of the learned weights)
 """
 from fractions import Fraction
 
@@ -63,6 +66,8 @@ WORKLOADS = {
     "batched_3d": dict(groups=_batched_3d(), seed=1, sweeps=100, iters=None, stop_on_flat=True),
     "large_3d": dict(groups=[(3, 48, particles(3, 48, 0.03), 16384)], seed=1, sweeps=100,
                      iters=None, stop_on_flat=True),
+    "held_out_3d": dict(groups=[(3, 24, particles(3, 24, 0.03), 4096)], seed=1, sweeps=100,
+                        iters=None, stop_on_flat=True),
 }
 
 
