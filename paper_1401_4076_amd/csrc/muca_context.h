@@ -43,12 +43,17 @@ struct muca_context {
   int layout = MUCA_LAYOUT_AUTO;  // requested
   int tuned = 0;                  // layout picked by mucaAutotune (0 = none yet)
   hipStream_t last_stream = nullptr;
-  // cooperative layouts: one task table per lanes-per-walker choice
+  // cooperative layouts: one task table per lanes-per-walker choice.  A task
+  // is one set of walkers (one block's worth of one group); block b runs
+  // tasks [first[b], first[b+1]) one after the other.
   struct Coop {
     SweepTask* d_tasks = nullptr;
-    int ntasks = 0;
-    size_t need = 0;       // LDS bytes for the walker state of the largest block
-  } coop[4];  // lanes per walker / walkers per wavefront: [0] 16/4, [1] 64/1, [2] 16/2, [3] 16/1
+    int32_t* d_first = nullptr;
+    int ntasks = 0, nblocks = 0;
+    size_t need = 0;       // LDS bytes for the walker state of the largest set
+  } coop[5];  // lanes per walker / walkers per wavefront: [0] 16/4, [1] 64/1, [2] 16/2,
+              // [3] 16/1, [4] 64/1 with one set per block (LOOK4)
+  int num_cu = 256;        // compute units of the device
   size_t tbl_bytes = 0;    // largest threshold table of one group
   size_t hist_bytes = 0;   // largest histogram of one group
   // captured iteration of mucaRun (replayed once per iteration)
@@ -85,7 +90,10 @@ struct muca_context {
     (void)hipFree(d_flat);
     (void)hipFree(d_iters);
     (void)hipFree(d_counter);
-    for (auto& q : coop) (void)hipFree(q.d_tasks);
+    for (auto& q : coop) {
+      (void)hipFree(q.d_tasks);
+      (void)hipFree(q.d_first);
+    }
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (run_stream) (void)hipStreamDestroy(run_stream);

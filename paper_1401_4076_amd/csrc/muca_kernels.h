@@ -17,10 +17,11 @@ __global__ void k_sweep_lane(const GroupDesc* groups, const int32_t* wgroup, uin
                              int32_t* H, const int32_t* active, int nwalkers, int sweeps,
                              uint32_t first_id, uint32_t seed32);
 template <int G, bool kLds, bool kTbl, bool kPipe>
-__global__ void k_sweep_sub(const GroupDesc* groups, const SweepTask* tasks, uint32_t* gbits,
-                            uint32_t* gpos, int32_t* gE, uint64_t* gT, const uint32_t* thr,
-                            int32_t* H, const int32_t* active, int sweeps, uint32_t first_id,
-                            uint32_t seed32, int tbl_words, int hist_words, int spread);
+__global__ void k_sweep_sub(const GroupDesc* groups, const SweepTask* tasks, const int32_t* first,
+                            uint32_t* gbits, uint32_t* gpos, int32_t* gE, uint64_t* gT,
+                            const uint32_t* thr, int32_t* H, const int32_t* active, int sweeps,
+                            uint32_t first_id, uint32_t seed32, int tbl_words, int hist_words,
+                            int spread);
 template <bool kTbl>
 __global__ void k_sweep_look(const GroupDesc* groups, const SweepTask* tasks, uint32_t* gbits,
                              uint32_t* gpos, int32_t* gE, uint64_t* gT, const uint32_t* thr,

@@ -132,10 +132,17 @@ int resolved_layout(muca_ctx c) {
   return c->tuned ? c->tuned : MUCA_LAYOUT_SUB16;
 }
 
-// Blocks of 256 threads hold 256/G walkers of one group; the blocks of the
-// groups are interleaved so that every CU receives a mix of lattice sizes.
-constexpr int kCoopLanes[4] = {16, 64, 16, 16};  // lanes per walker
-constexpr int kCoopSpread[4] = {1, 1, 2, 4};     // 16-lane rows per walker row used
+// A set is up to 256/G/spread walkers of one group (one block's worth).
+// When the sets outnumber the CUs but are not a whole multiple of them, the
+// sets are packed longest first (V per sweep) into a whole number of blocks
+// per CU, a block running its sets one after the other: otherwise the few
+// blocks beyond a full round share SIMDs with the long chains and stretch the
+// launch (258 sets of 16 walkers on 256 CUs cost 30 % in the batched 2D
+// workload).  Otherwise one set per block, the groups interleaved so that
+// every CU receives a mix of lattice sizes.
+constexpr int kCoopLanes[5] = {16, 64, 16, 16, 64};  // lanes per walker
+constexpr int kCoopSpread[5] = {1, 1, 2, 4, 1};      // 16-lane rows per walker row used
+constexpr bool kCoopPacked[5] = {true, true, true, true, false};
 
 int build_coop(muca_ctx c, int which) {
   auto& q = c->coop[which];
@@ -151,23 +158,53 @@ int build_coop(muca_ctx c, int which) {
     need = std::max(need, (size_t)wpb * (size_t)(g.words + 2 * g.N) * sizeof(uint32_t));
     c->hist_bytes = std::max(c->hist_bytes, (size_t)g.nbins * sizeof(int32_t));
   }
-  std::vector<SweepTask> tasks;
+  std::vector<SweepTask> sets;
   for (size_t r = 0;; ++r) {
     bool any = false;
     for (auto& v : per)
       if (r < v.size()) {
-        tasks.push_back(v[r]);
+        sets.push_back(v[r]);
         any = true;
       }
     if (!any) break;
   }
+  const int n = (int)sets.size(), C = std::max(1, c->num_cu);
+  std::vector<SweepTask> tasks;
+  std::vector<int32_t> first;
+  if (!kCoopPacked[which] || n <= C || n % C == 0) {
+    tasks = sets;
+    for (int b = 0; b <= n; ++b) first.push_back(b);
+  } else {
+    const int B = (n / C) * C;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return c->g[sets[a].group].V > c->g[sets[b].group].V;
+    });
+    std::vector<std::vector<int>> blk(B);
+    std::vector<int64_t> load(B, 0);
+    for (int i : order) {  // longest first onto the least loaded block (lowest index on ties)
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      blk[b].push_back(i);
+      load[b] += c->g[sets[i].group].V;
+    }
+    for (int b = 0; b < B; ++b) {
+      first.push_back((int32_t)tasks.size());
+      for (int i : blk[b]) tasks.push_back(sets[i]);
+    }
+    first.push_back((int32_t)tasks.size());
+  }
   q.ntasks = (int)tasks.size();
+  q.nblocks = (int)first.size() - 1;
   q.need = need;
   c->tbl_bytes = 0;
   for (const auto& g : c->g)
     c->tbl_bytes = std::max(c->tbl_bytes, (size_t)g.nbins * (size_t)g.nd * sizeof(uint32_t));
   if (int r = dev_alloc(&q.d_tasks, tasks.size())) return r;
+  if (int r = dev_alloc(&q.d_first, first.size())) return r;
   HIP_TRY(hipMemcpy(q.d_tasks, tasks.data(), sizeof(SweepTask) * tasks.size(),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(q.d_first, first.data(), sizeof(int32_t) * first.size(),
                     hipMemcpyHostToDevice));
   return MUCA_OK;
 }
@@ -194,9 +231,9 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
                                    : muca::k_sweep_sub<16, false, false, true>)
                         : (tbl_lds ? muca::k_sweep_sub<G, false, true, false>
                                    : muca::k_sweep_sub<G, false, false, false>);
-  hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
-                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active, sweeps,
-                     c->first_id, c->seed32, tbl_words,
+  hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
+                     q.d_first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active,
+                     sweeps, c->first_id, c->seed32, tbl_words,
                      state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0, kCoopSpread[which]);
   LAUNCH_CHECK();
   return MUCA_OK;
@@ -205,8 +242,8 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
 // Lookahead layout: blocks of four walkers (one per wavefront), walker state
 // and block histogram in LDS; falls back to SUB64 when they do not fit.
 int launch_look(muca_ctx c, int sweeps, int32_t* H, const int32_t* active, hipStream_t s) {
-  if (int r = build_coop(c, 1)) return r;
-  const auto& q = c->coop[1];
+  if (int r = build_coop(c, 4)) return r;
+  const auto& q = c->coop[4];
   const size_t cap = std::min(c->lds_limit, c->lds_device);
   if (c->bricked || q.need + c->hist_bytes > cap) return launch_coop<64>(c, 1, sweeps, H, active, s);
   const size_t state = q.need + c->hist_bytes;
@@ -353,6 +390,9 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
     int v = 0;
     HIP_TRY_DEL(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     c->lds_device = (size_t)v;
+    int cus = 0;
+    HIP_TRY_DEL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    c->num_cu = std::max(1, cus);
     // allow every cooperative kernel the device's full LDS per block (set
     // once here, outside any stream capture)
     const void* kernels[] = {
@@ -699,7 +739,7 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
       c->graph_exec = nullptr;
       c->graph = nullptr;
       // task tables and kernel attributes are set up outside the capture
-      for (int which = 0; which < 4; ++which)
+      for (int which = 0; which < 5; ++which)
         if (int r = build_coop(c, which)) return r;
       HIP_TRY(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
       const int r = enqueue_iteration(rs);

@@ -398,21 +398,14 @@ __device__ __forceinline__ void unrolled16(Walker<G, kLds, kTbl>& W, int nb) {
   }
 }
 
-}  // namespace
-
+// One set of walkers (one task) for `sweeps` sweeps, by the whole block.
 template <int G, bool kLds, bool kTbl, bool kPipe>
-__global__ void __launch_bounds__(256) k_sweep_sub(
-    const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
+__device__ __forceinline__ void run_set(
+    const GroupDesc* __restrict__ groups, const SweepTask task, uint32_t* smem,
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
     uint64_t* __restrict__ gT, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
     const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
     int tbl_words, int hist_words, int spread) {
-  static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
-  static_assert(!(kLds && kPipe), "the pipelined gather is for device-memory state");
-  // LDS: [threshold table (tbl_words)] [block histogram (hist_words, LDS-state mode)]
-  //      [walker slots]
-  extern __shared__ uint32_t smem[];
-  const SweepTask task = tasks[blockIdx.x];
   if (active && !active[task.group]) return;  // uniform per block
   const GroupDesc g = groups[task.group];
   Walker<G, kLds, kTbl> W;
@@ -559,35 +552,59 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   }
 }
 
+}  // namespace
+
+// Block b runs tasks [first[b], first[b + 1]) one after the other.
+template <int G, bool kLds, bool kTbl, bool kPipe>
+__global__ void __launch_bounds__(256) k_sweep_sub(
+    const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
+    const int32_t* __restrict__ first, uint32_t* __restrict__ gbits,
+    uint32_t* __restrict__ gpos, int32_t* __restrict__ gE, uint64_t* __restrict__ gT,
+    const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
+    const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
+    int tbl_words, int hist_words, int spread) {
+  static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
+  static_assert(!(kLds && kPipe), "the pipelined gather is for device-memory state");
+  // LDS: [threshold table (tbl_words)] [block histogram (hist_words, LDS-state mode)]
+  //      [walker slots]
+  extern __shared__ uint32_t smem[];
+  const int t0 = first[blockIdx.x], t1 = first[blockIdx.x + 1];
+  for (int ti = t0; ti < t1; ++ti) {
+    if (ti > t0) __syncthreads();  // the previous set is out of LDS
+    run_set<G, kLds, kTbl, kPipe>(groups, tasks[ti], smem, gbits, gpos, gE, gT, thr, H, active,
+                                  sweeps, first_id, seed32, tbl_words, hist_words, spread);
+  }
+}
+
 template __global__ void k_sweep_sub<16, true, true, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, true, false, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, true, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, false, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, true, true>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, false, true>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, true, true, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, true, false, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, false, true, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<64, false, false, false>(
-    const GroupDesc*, const SweepTask*, uint32_t*, uint32_t*, int32_t*, uint64_t*,
-    const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 
 }  // namespace muca

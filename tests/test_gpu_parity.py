@@ -198,6 +198,25 @@ def test_sweep_matches_oracle(groups, sweeps, variant):
     assert_walkers_equal(ctx, ref, range(ctx.nwalkers))
 
 
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_packed_blocks_match_oracle(variant):
+    # more walker sets than CUs, not a whole multiple: sets are packed longest
+    # first into whole rounds of blocks, some blocks running two sets
+    groups = [(2, 4, 5, 2056), (2, 6, 10, 2056), (3, 4, 9, 20, -20, 0)]
+    say("packed", groups, variant)
+    ctx = make_ctx(groups, 6, variant)
+    ref = O.RefContext(groups, seed=6)
+    lnW = W.random_lnW(ctx.total_bins, seed=7, scale=1.0)
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+    for call in range(2):
+        ctx.sweep(dev_f64(lnW), 3, H)
+        rH = ref.sweep(lnW, 3)
+        torch.cuda.synchronize()
+        assert np.array_equal(H.cpu().numpy(), rH), call
+    rng = np.random.default_rng(0)
+    assert_walkers_equal(ctx, ref, sorted(rng.choice(ctx.nwalkers, 150, replace=False)))
+
+
 def test_sweep_active_mask():
     groups = [(2, 8, 16, 4), (3, 4, 5, 3), (2, 6, 4, 5)]
     ctx = M.Context(groups, seed=4)
