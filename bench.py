@@ -101,6 +101,16 @@ def split_walkers(groups, parts):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(groups, seed, sample_sweeps, threads):
     """The oracle on the host, one instance per thread over disjoint ranges of
     global walker ids (the paper's one-process-per-core scheme).  The oracle
@@ -119,8 +129,8 @@ def cpu_baseline(groups, seed, sample_sweeps, threads):
     assert sum(int(H.sum()) for H in Hs) == total * sample_sweeps
     return {"value": n / dt, "unit": "attempts/s", "cores": len(refs), "kind": "oracle",
             "sample": f"all {total} walkers x {sample_sweeps} sweeps ({n:.3g} attempts, flat "
-                      f"weights) in {dt:.1f} s on {len(refs)} threads, one oracle instance per "
-                      f"thread over disjoint walker ranges"}
+                      f"weights) in {dt:.1f} s on {len(refs)} threads ({cpu_model()}), one "
+                      f"oracle instance per thread over disjoint walker ranges"}
 
 
 def calibrate_copy(nbytes):

@@ -42,6 +42,10 @@ def main():
     ap.add_argument("--train-sweeps", type=int, default=1000)
     ap.add_argument("--train-max-iters", type=int, default=400)
     ap.add_argument("--steps", type=int, default=4000, help="Adam steps")
+    ap.add_argument("--extra", default="",
+                    help="additional training lattices d:L:rho:walkers[,...], converged in one "
+                         "context with --extra-sweeps sweeps per iteration")
+    ap.add_argument("--extra-sweeps", type=int, default=200)
     ap.add_argument("--target", default="large_3d")
     ap.add_argument("--target-walkers", type=int, default=None)
     ap.add_argument("--target-sweeps", type=int, default=None)
@@ -85,6 +89,26 @@ def train_stage(args, out):
         done = [g for g, f in enumerate(run["flat"]) if f]
         out["train"].append({"workload": name, "groups": [list(g) for g in wl["groups"]],
                              "sweeps": wl["sweeps"], "iters": list(run["iters"]),
+                             "flat": list(run["flat"]), "seconds": run["seconds"]})
+        if done:
+            X, T = LR.table_rows(run["ctx"], run["lnW"], done)
+            Xs.append(X)
+            Ts.append(T)
+        run["ctx"].close()
+    if args.extra:
+        groups = []
+        for spec in args.extra.split(","):
+            d, L, rho, walkers = spec.split(":")
+            d, L, walkers = int(d), int(L), int(walkers)
+            groups.append((d, L, W.particles(d, L, float(rho)), walkers))
+        log(f"extra tables: groups {groups} sweeps {args.extra_sweeps}")
+        run = LR.converge(groups, args.seed, args.extra_sweeps, args.train_max_iters,
+                          chunk=args.chunk, max_seconds=args.max_seconds,
+                          progress=lambda n, f, s, d: log(f"  extra: {n} iterations, flat {list(f)}, "
+                                                          f"{s:.1f} s"))
+        done = [g for g, f in enumerate(run["flat"]) if f]
+        out["train"].append({"workload": "extra", "groups": [list(g) for g in groups],
+                             "sweeps": args.extra_sweeps, "iters": list(run["iters"]),
                              "flat": list(run["flat"]), "seconds": run["seconds"]})
         if done:
             X, T = LR.table_rows(run["ctx"], run["lnW"], done)
