@@ -49,26 +49,40 @@ __device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
   else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Bit `bit` (only its low 5 bits count) of word w.  v_bfe_u32 reads only the
+// low 5 bits of its offset, so a linear site can be passed unmasked.
+__device__ __forceinline__ uint32_t bit_at(uint32_t w, uint32_t bit) {
+  return __builtin_amdgcn_ubfe(w, bit, 1u);
+}
+
+// Word and bit of a linear site; the site itself serves as the bit (see
+// bit_at).
+__device__ __forceinline__ BitRef linear_ref(uint32_t s) {
+  return BitRef{__builtin_amdgcn_ubfe(s, 5u, 27u), s};
+}
+
 // Word and bit of a site: linear in LDS; in device memory the group's layout
 // (linear or bricked, see bit_ref).
 template <bool kLds>
 __device__ __forceinline__ BitRef locate(const GroupDesc& g, uint32_t s, uint32_t xyz) {
-  if constexpr (kLds) return BitRef{s >> 5, s & 31u};
+  if constexpr (kLds) return linear_ref(s);
   else return bit_ref(g, s, xyz);
 }
 
+// The move s_o -> s_n: s_o is occupied and s_n empty, so toggling both bits
+// clears the one and sets the other.
 template <bool kLds>
 __device__ __forceinline__ void flip(const GroupDesc& g, uint32_t* bits, uint32_t so,
                                      uint32_t sox, uint32_t sn, uint32_t snx) {
   const BitRef a = locate<kLds>(g, so, sox), b = locate<kLds>(g, sn, snx);
   if constexpr (kLds) {
-    atomicAnd(&bits[a.word], ~(1u << a.bit));
-    atomicOr(&bits[b.word], 1u << b.bit);
+    atomicXor(&bits[a.word], 1u << (a.bit & 31u));
+    atomicXor(&bits[b.word], 1u << (b.bit & 31u));
   } else {
-    __hip_atomic_fetch_and(&bits[a.word], ~(1u << a.bit), __ATOMIC_RELAXED,
+    __hip_atomic_fetch_xor(&bits[a.word], 1u << (a.bit & 31u), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_or(&bits[b.word], 1u << b.bit, __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_xor(&bits[b.word], 1u << (b.bit & 31u), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
@@ -117,7 +131,7 @@ __device__ __forceinline__ uint32_t role_locate(const GroupDesc& g, const NbrRol
   const bool edge = ((xyz >> r.shift) & kXyzMask) == r.edge;
   const uint32_t s = lin + (uint32_t)(edge ? r.wrap : r.step);
   if constexpr (kLds) {
-    at = BitRef{s >> 5, s & 31u};
+    at = linear_ref(s);
   } else {
     at = bit_ref(g, s, xyz + (edge ? r.cwrap : r.cstep));
   }
@@ -156,7 +170,7 @@ struct Walker {
   int32_t* hist;
   int ls, base, d2, nd;
   uint32_t V, N, key0, seed32;
-  int32_t E;
+  int32_t E;  // energy minus the window's e_lo (bin index) during the launch
   uint64_t t;
   uint32_t Trow;
   // lane roles of the main gather: [0,2d) nbr(s_o), 2d: c2, 2d+1: c3,
@@ -225,7 +239,7 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
     if constexpr (!kLds) {
       const BitRef a3 = locate<kLds>(g, c3, c3x);
       const uint32_t w3 = ld<kLds>(&W.bits[a3.word]);
-      c3free = !((w3 >> a3.bit) & 1u);
+      c3free = !bit_at(w3, a3.bit);
     }
     if (!c3free) {
       // both candidates occupied: words 0..3 of blocks 1, 2, ... in order
@@ -237,10 +251,10 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
         const uint32_t word = pick4(q, l4);
         const uint32_t cand = draw(word, W.V);
         uint32_t vv = 0;
-        BitRef ac{cand >> 5, cand & 31u};
+        BitRef ac = linear_ref(cand);
         if constexpr (!kLds) ac = bit_of(g, cand);
         if (W.ls < 4) vv = ld<kLds>(&W.bits[ac.word]);
-        const bool fr = (W.ls < 4) && !((vv >> ac.bit) & 1u);
+        const bool fr = (W.ls < 4) && !bit_at(vv, ac.bit);
         const uint32_t fm = sub_mask<G>(__ballot(fr), W.base) & 0xFu;
         if (fm) {
           const int first = __ffs(fm) - 1;
@@ -256,7 +270,7 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
     uint32_t v3 = 0;
     const bool on3 = W.ls < d2;
     if (on3) v3 = ld<kLds>(&W.bits[at3.word]);
-    const bool occ3 = on3 && ((v3 >> at3.bit) & 1u) && (s3 != so);
+    const bool occ3 = on3 && bit_at(v3, at3.bit) && (s3 != so);
     kn = __popc(sub_mask<G>(__ballot(occ3), W.base));
   }
   const int dE = ko - kn;
@@ -280,9 +294,9 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   W.b_so = take ? sn : W.b_so;
   W.b_sox = take ? snx : W.b_sox;
   W.E += acc ? dE : 0;
-  // (E - e_lo) < 2^24 and nd <= 13: a full-rate 24-bit product
+  // W.E = E - e_lo < 2^24 and nd <= 13: a full-rate 24-bit product
   if (acc && dE != 0 && W.ls < W.nd)
-    W.Trow = W.th[__umul24((uint32_t)(W.E - g.e_lo), (uint32_t)W.nd) + (uint32_t)W.ls];
+    W.Trow = W.th[__umul24((uint32_t)W.E, (uint32_t)W.nd) + (uint32_t)W.ls];
 }
 
 // One attempt with the broadcast values of attempt ta (state in LDS).
@@ -301,7 +315,7 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   // (accepts(): T = kAlways or u < T; lanes past the row hold 0, never); the
   // entry of the attempt's dE decides
   const uint64_t ok = __ballot(u < W.Trow) | __ballot(W.Trow == kAlways);
-  const uint32_t m = (uint32_t)(__ballot(((v >> at.bit) & 1u) != 0u) >> W.base);
+  const uint32_t m = (uint32_t)(__ballot(bit_at(v, at.bit) != 0u) >> W.base);
   const uint32_t nm = m & ~(uint32_t)(__ballot(site == so) >> W.base);  // occupied, not s_o
   resolve<G, kLds, kTbl>(W, k, u, c2, c2x, c3, c3x, so, sox, ta, m, nm, ok);
 }
@@ -355,7 +369,7 @@ __device__ __forceinline__ Pend fetch64(const Walker<G, kLds, kTbl>& W, int a) {
 template <int G, bool kLds, bool kTbl>
 __device__ __forceinline__ void decide(Walker<G, kLds, kTbl>& W, Pend p, uint64_t ta) {
   const uint64_t ok = __ballot(p.u < W.Trow) | __ballot(W.Trow == kAlways);  // as in attempt()
-  uint32_t bit = (p.v >> p.sh) & 1u;
+  uint32_t bit = bit_at(p.v, p.sh);
   bit = (p.site == W.pm_sn) ? 1u : ((p.site == W.pm_so) ? 0u : bit);
   const bool moved = p.k == W.pm_k;
   if (__ballot(moved) != 0ull) {
@@ -364,7 +378,7 @@ __device__ __forceinline__ void decide(Walker<G, kLds, kTbl>& W, Pend p, uint64_
     BitRef at;
     const uint32_t site = gather_site(W, p.so, p.sox, p.c2, p.c2x, p.c3, p.c3x, at);
     const uint32_t v = ld<kLds>(&W.bits[at.word]);
-    bit = moved ? ((v >> at.bit) & 1u) : bit;
+    bit = moved ? bit_at(v, at.bit) : bit;
     p.site = moved ? site : p.site;
   }
   const uint32_t m = (uint32_t)(__ballot(bit != 0u) >> W.base);
@@ -472,9 +486,9 @@ __device__ __forceinline__ void run_set(
     else W.hist = H + g.bin_off;
     W.key0 = first_id + (uint32_t)w;
     W.seed32 = seed32;
-    W.E = gE[w];
+    W.E = gE[w] - g.e_lo;
     W.t = gT[w];
-    W.Trow = (ls < W.nd) ? W.th[(W.E - g.e_lo) * W.nd + ls] : 0u;
+    W.Trow = (ls < W.nd) ? W.th[W.E * W.nd + ls] : 0u;
     // A batch never straddles the end of a sweep (the last batch of a sweep
     // may be short; its spare lanes compute attempts that the next batch
     // redoes), so the histogram entry is taken after the batch.
@@ -500,7 +514,7 @@ __device__ __forceinline__ void run_set(
           }
           W.t += (uint64_t)nb;
         }
-        if (ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+        if (ls == 0) atomicAdd(&W.hist[W.E], 1);
       }
     } else {
       W.pm_k = W.pm_so = W.pm_sn = kNone;
@@ -532,11 +546,11 @@ __device__ __forceinline__ void run_set(
           decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)(nb - 1));
           W.t += (uint64_t)nb;
         }
-        if (ls == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+        if (ls == 0) atomicAdd(&W.hist[W.E], 1);
       }
     }
     if (ls == 0) {
-      gE[w] = W.E;
+      gE[w] = W.E + g.e_lo;
       gT[w] = W.t;
     }
   }

@@ -29,6 +29,15 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_binding_constants_match_the_header():
+    text = open(HEADER).read()
+    defs = {k: int(v) for k, v in re.findall(r"^#define (MUCA_\w+)\s+\(?(-?\d+)\)?", text, re.M)}
+    assert len(defs) >= 15
+    for k, v in defs.items():
+        assert getattr(M, k) == v, k
+    assert M.LAYOUTS == tuple(range(1, defs["MUCA_NUM_LAYOUTS"]))
+
+
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(M.LIB_PATH)
     for name in declared_functions():
