@@ -280,6 +280,16 @@ def test_run_reduced_workloads(name, walkers, sweeps, iters, variant):
               variant=variant)
 
 
+@pytest.mark.parametrize("variant", [VARIANTS[1], VARIANTS[2], VARIANTS[8], VARIANTS[9]],
+                         ids=[VARIANT_IDS[1], VARIANT_IDS[2], VARIANT_IDS[8], VARIANT_IDS[9]])
+def test_run_with_packed_blocks_until_flat(variant):
+    # more walker sets than CUs (packed blocks) inside the captured iteration
+    # loop, groups stopping at different iterations
+    groups = [(2, 4, 5, 2056), (2, 6, 10, 2056), (3, 4, 9, 20, -20, 0)]
+    rc, it, fl = _run_both(groups, 3, 20, 30, rule=0, stop_on_flat=True, variant=variant)
+    assert list(fl) == [1, 1, 0] and list(it) == [2, 3, 30]  # as the oracle (checked above)
+
+
 FLAT_GROUPS = [(2, 4, 5, 64, -5, 0), (2, 6, 10, 16, 0, 0), (3, 4, 4, 16, -4, 0),
                (2, 8, 12, 16, 0, 0), (2, 7, 9, 8, 0, 0)]
 
