@@ -221,16 +221,16 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
   const bool tbl_lds = c->lds_limit > 0 && state + c->tbl_bytes <= cap;
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
   const int tbl_words = tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0;
-  // With state in device memory the 16-lane layouts with spread rows
-  // (SUB16X2, SUB16X1) pipeline their gathers; SUB16 and SUB64 do not (the
-  // pipelined kernel needs more registers, which costs occupancy).
-  const bool pipe = G == 16 && kCoopSpread[which] > 1;
+  // With state in device memory the 16-lane layouts issue the next attempt's
+  // gather before deciding the current one (kPipe); the 64-lane layout does
+  // not (pipelined, it ran slower on the large 3D lattices).
+  const bool pipe = G == 16;
   auto kern = state_lds ? (tbl_lds ? muca::k_sweep_sub<G, true, true, false>
                                    : muca::k_sweep_sub<G, true, false, false>)
             : pipe      ? (tbl_lds ? muca::k_sweep_sub<16, false, true, true>
                                    : muca::k_sweep_sub<16, false, false, true>)
-                        : (tbl_lds ? muca::k_sweep_sub<G, false, true, false>
-                                   : muca::k_sweep_sub<G, false, false, false>);
+                        : (tbl_lds ? muca::k_sweep_sub<64, false, true, false>
+                                   : muca::k_sweep_sub<64, false, false, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
                      q.d_first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active,
                      sweeps, c->first_id, c->seed32, tbl_words,
@@ -398,8 +398,6 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
     const void* kernels[] = {
         (const void*)muca::k_sweep_sub<16, true, true, false>,
         (const void*)muca::k_sweep_sub<16, true, false, false>,
-        (const void*)muca::k_sweep_sub<16, false, true, false>,
-        (const void*)muca::k_sweep_sub<16, false, false, false>,
         (const void*)muca::k_sweep_sub<16, false, true, true>,
         (const void*)muca::k_sweep_sub<16, false, false, true>,
         (const void*)muca::k_sweep_sub<64, true, true, false>,

@@ -25,8 +25,9 @@
 // coordinates) lives in LDS for the whole launch; otherwise occupation bits
 // and sites stay in device memory (workgroup-coherent accesses, the group's
 // bit layout: linear or bricked, see bit_ref) and the coordinates of s_o are
-// recomputed in the batch phase.  kPipe (device memory only): the gather of
-// the next attempt is issued before the current one is decided.
+// recomputed in the batch phase.  kPipe (device memory only; the 16-lane
+// layouts): the gather of the next attempt is issued before the current one
+// is decided.
 // spread (16 lanes only): walkers sit in every spread-th 16-lane row, so a
 // small population fills more wavefronts (layouts SUB16X2, SUB16X1).
 #include "muca_kernels.h"
@@ -594,12 +595,6 @@ template __global__ void k_sweep_sub<16, true, true, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, true, false, false>(
-    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<16, false, true, false>(
-    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
-template __global__ void k_sweep_sub<16, false, false, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
 template __global__ void k_sweep_sub<16, false, true, true>(
