@@ -133,13 +133,12 @@ int resolved_layout(muca_ctx c) {
 }
 
 // A set is up to 256/G/spread walkers of one group (one block's worth).
-// When the sets outnumber the CUs but are not a whole multiple of them, the
-// sets are packed longest first (V per sweep) into a whole number of blocks
-// per CU, a block running its sets one after the other: otherwise the few
-// blocks beyond a full round share SIMDs with the long chains and stretch the
-// launch (258 sets of 16 walkers on 256 CUs cost 30 % in the batched 2D
-// workload).  Otherwise one set per block, the groups interleaved so that
-// every CU receives a mix of lattice sizes.
+// When the sets outnumber the CUs, they are packed longest first (V per
+// sweep) into a whole number of blocks per CU, a block running its sets one
+// after the other: otherwise the few blocks beyond a full round share SIMDs
+// with the long chains and stretch the launch (258 sets of 16 walkers on 256
+// CUs cost 30 % in the batched 2D workload).  Otherwise one set per block,
+// the groups interleaved so that every CU receives a mix of lattice sizes.
 constexpr int kCoopLanes[5] = {16, 64, 16, 16, 64};  // lanes per walker
 constexpr int kCoopSpread[5] = {1, 1, 2, 4, 1};      // 16-lane rows per walker row used
 constexpr bool kCoopPacked[5] = {true, true, true, true, false};
@@ -171,7 +170,7 @@ int build_coop(muca_ctx c, int which) {
   const int n = (int)sets.size(), C = std::max(1, c->num_cu);
   std::vector<SweepTask> tasks;
   std::vector<int32_t> first;
-  if (!kCoopPacked[which] || n <= C || n % C == 0) {
+  if (!kCoopPacked[which] || n <= C) {
     tasks = sets;
     for (int b = 0; b <= n; ++b) first.push_back(b);
   } else {
@@ -188,7 +187,15 @@ int build_coop(muca_ctx c, int which) {
       blk[b].push_back(i);
       load[b] += c->g[sets[i].group].V;
     }
-    for (int b = 0; b < B; ++b) {
+    // B / C rounds of blocks share the CUs.  Blocks sorted by load, with
+    // every other round in reverse order, so that a CU's longest block gets
+    // the shortest partners (the dispatcher hands out each round across the
+    // CUs in order).
+    std::vector<int> bo(B);
+    for (int b = 0; b < B; ++b) bo[b] = b;
+    std::stable_sort(bo.begin(), bo.end(), [&](int a, int b) { return load[a] > load[b]; });
+    for (int r = 1; r < B / C; r += 2) std::reverse(bo.begin() + r * C, bo.begin() + (r + 1) * C);
+    for (int b : bo) {
       first.push_back((int32_t)tasks.size());
       for (int i : blk[b]) tasks.push_back(sets[i]);
     }
