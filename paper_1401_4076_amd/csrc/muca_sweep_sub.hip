@@ -145,12 +145,19 @@ __device__ __forceinline__ uint32_t sub_mask(uint64_t ballot, int base) {
   else return (uint32_t)(ballot >> base) & ((1u << G) - 1u);
 }
 
-// Broadcast lane A (compile-time) of each 16-lane row, or lane a of the wave.
+// Broadcast of lane A of each 16-lane row: one 64-bit DPP move (row_newbcast
+// is among the DPP controls of gfx950's 64-bit moves) carries two values.
 // Every lane of every row is written, so no old value is needed.
 template <int A>
-__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150 + A, 0xF, 0xF, true);
+__device__ __forceinline__ uint64_t row_bcast64(uint64_t v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + A, 0xF, 0xF, true);
 }
+
+__device__ __forceinline__ uint64_t pair(uint32_t low, uint32_t high) {
+  return (uint64_t)low | ((uint64_t)high << 32);
+}
+__device__ __forceinline__ uint32_t lo(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t hi(uint64_t v) { return (uint32_t)(v >> 32); }
 
 // One attempt's broadcast values, this lane's gather site, the site's bit in
 // the loaded word, and the word (pipelined device-memory path).
@@ -184,7 +191,9 @@ struct Walker {
   bool role_so, role_c3, full;
   NbrRole role2;  // lanes [0, 2d): nbr of s_n in the second gather
   // batch values of lane ls (attempt t + ls)
-  uint32_t b_k, b_u, b_c2, b_c2x, b_c3, b_c3x, b_so, b_sox;
+  // kept in pairs (low word, high word) so that one 64-bit DPP broadcast
+  // moves two values: (k, u), (c2, c2x), (c3, c3x), (s_o, s_o coordinates)
+  uint64_t b_ku, b_c2p, b_c3p, b_sop;
   // device-memory path: the previous attempt's move (particle, old and new
   // site; kNone if rejected) and the fetch of the next batch's first attempt
   uint32_t pm_k, pm_so, pm_sn, pm_snx;
@@ -196,15 +205,16 @@ __device__ __forceinline__ void batch_phase(Walker<G, kLds, kTbl>& W, uint64_t t
   const GroupDesc& g = *W.g;
   const uint64_t tl = t0 + (uint64_t)W.ls;
   const U4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), 0u, 0u, W.key0, W.seed32);
-  W.b_k = draw(r.x, W.N);
-  W.b_u = r.y;
-  W.b_c2 = draw(r.z, W.V);
-  W.b_c3 = draw(r.w, W.V);
-  W.b_c2x = site_xyz(g, W.b_c2);
-  W.b_c3x = site_xyz(g, W.b_c3);
-  W.b_so = ld<kLds>(&W.plin[W.b_k]);
-  if constexpr (kLds) W.b_sox = W.pxyz[W.b_k];
-  else W.b_sox = site_xyz(g, W.b_so);
+  const uint32_t k = draw(r.x, W.N);
+  const uint32_t c2 = draw(r.z, W.V), c3 = draw(r.w, W.V);
+  const uint32_t so = ld<kLds>(&W.plin[k]);
+  uint32_t sox;
+  if constexpr (kLds) sox = W.pxyz[k];
+  else sox = site_xyz(g, so);
+  W.b_ku = pair(k, r.y);
+  W.b_c2p = pair(c2, site_xyz(g, c2));
+  W.b_c3p = pair(c3, site_xyz(g, c3));
+  W.b_sop = pair(so, sox);
 }
 
 // This lane's site in the main gather of an attempt and its bit location.
@@ -291,9 +301,8 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
     W.pm_snx = snx;
   }
   // later attempts of this batch that chose the same particle see its new site
-  const bool take = acc && (W.b_k == k);
-  W.b_so = take ? sn : W.b_so;
-  W.b_sox = take ? snx : W.b_sox;
+  const bool take = acc && (lo(W.b_ku) == k);
+  W.b_sop = take ? pair(sn, snx) : W.b_sop;
   W.E += acc ? dE : 0;
   // W.E = E - e_lo < 2^24 and nd <= 13: a full-rate 24-bit product
   if (acc && dE != 0 && W.ls < W.nd)
@@ -312,6 +321,7 @@ __device__ __forceinline__ void attempt(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   // ballots need no lane predicate.  Bits above the walker's 16 may belong
   // to the next walker of the wave; every use selects its own bits.
   const uint32_t v = ld<kLds>(&W.bits[at.word]);
+  __builtin_amdgcn_sched_barrier(0);  // issue the gather before waiting on the row below
   // while the gather is in flight: every lane of the threshold row tests u
   // (accepts(): T = kAlways or u < T; lanes past the row hold 0, never); the
   // entry of the attempt's dE decides
@@ -340,14 +350,16 @@ __device__ __forceinline__ void gather(const Walker<G, kLds, kTbl>& W, Pend& p) 
 template <int A, int G, bool kLds, bool kTbl>
 __device__ __forceinline__ Pend fetch16(const Walker<G, kLds, kTbl>& W) {
   Pend p;
-  p.k = row_bcast<A>(W.b_k);
-  p.u = row_bcast<A>(W.b_u);
-  p.c2 = row_bcast<A>(W.b_c2);
-  p.c2x = row_bcast<A>(W.b_c2x);
-  p.c3 = row_bcast<A>(W.b_c3);
-  p.c3x = row_bcast<A>(W.b_c3x);
-  p.so = row_bcast<A>(W.b_so);
-  p.sox = row_bcast<A>(W.b_sox);
+  const uint64_t ku = row_bcast64<A>(W.b_ku), c2p = row_bcast64<A>(W.b_c2p);
+  const uint64_t c3p = row_bcast64<A>(W.b_c3p), sop = row_bcast64<A>(W.b_sop);
+  p.k = lo(ku);
+  p.u = hi(ku);
+  p.c2 = lo(c2p);
+  p.c2x = hi(c2p);
+  p.c3 = lo(c3p);
+  p.c3x = hi(c3p);
+  p.so = lo(sop);
+  p.sox = hi(sop);
   gather(W, p);
   return p;
 }
@@ -355,14 +367,14 @@ __device__ __forceinline__ Pend fetch16(const Walker<G, kLds, kTbl>& W) {
 template <int G, bool kLds, bool kTbl>
 __device__ __forceinline__ Pend fetch64(const Walker<G, kLds, kTbl>& W, int a) {
   Pend p;
-  p.k = __builtin_amdgcn_readlane(W.b_k, a);
-  p.u = __builtin_amdgcn_readlane(W.b_u, a);
-  p.c2 = __builtin_amdgcn_readlane(W.b_c2, a);
-  p.c2x = __builtin_amdgcn_readlane(W.b_c2x, a);
-  p.c3 = __builtin_amdgcn_readlane(W.b_c3, a);
-  p.c3x = __builtin_amdgcn_readlane(W.b_c3x, a);
-  p.so = __builtin_amdgcn_readlane(W.b_so, a);
-  p.sox = __builtin_amdgcn_readlane(W.b_sox, a);
+  p.k = __builtin_amdgcn_readlane(lo(W.b_ku), a);
+  p.u = __builtin_amdgcn_readlane(hi(W.b_ku), a);
+  p.c2 = __builtin_amdgcn_readlane(lo(W.b_c2p), a);
+  p.c2x = __builtin_amdgcn_readlane(hi(W.b_c2p), a);
+  p.c3 = __builtin_amdgcn_readlane(lo(W.b_c3p), a);
+  p.c3x = __builtin_amdgcn_readlane(hi(W.b_c3p), a);
+  p.so = __builtin_amdgcn_readlane(lo(W.b_sop), a);
+  p.sox = __builtin_amdgcn_readlane(hi(W.b_sop), a);
   gather(W, p);
   return p;
 }
@@ -405,9 +417,10 @@ template <int A, int G, bool kLds, bool kTbl>
 __device__ __forceinline__ void unrolled16(Walker<G, kLds, kTbl>& W, int nb) {
   if constexpr (A < 16) {
     if (A < nb) {
-      attempt<G, kLds, kTbl>(W, row_bcast<A>(W.b_k), row_bcast<A>(W.b_u), row_bcast<A>(W.b_c2),
-                       row_bcast<A>(W.b_c2x), row_bcast<A>(W.b_c3), row_bcast<A>(W.b_c3x),
-                       row_bcast<A>(W.b_so), row_bcast<A>(W.b_sox), W.t + (uint64_t)A);
+      const uint64_t ku = row_bcast64<A>(W.b_ku), c2p = row_bcast64<A>(W.b_c2p);
+      const uint64_t c3p = row_bcast64<A>(W.b_c3p), sop = row_bcast64<A>(W.b_sop);
+      attempt<G, kLds, kTbl>(W, lo(ku), hi(ku), lo(c2p), hi(c2p), lo(c3p), hi(c3p), lo(sop),
+                             hi(sop), W.t + (uint64_t)A);
       unrolled16<A + 1, G, kLds, kTbl>(W, nb);
     }
   }
@@ -502,14 +515,14 @@ __device__ __forceinline__ void run_set(
             unrolled16<0, G, kLds, kTbl>(W, nb);
           } else {
             for (int a = 0; a < nb; ++a) {
-              attempt<G, kLds, kTbl>(W, __builtin_amdgcn_readlane(W.b_k, a),
-                                     __builtin_amdgcn_readlane(W.b_u, a),
-                                     __builtin_amdgcn_readlane(W.b_c2, a),
-                                     __builtin_amdgcn_readlane(W.b_c2x, a),
-                                     __builtin_amdgcn_readlane(W.b_c3, a),
-                                     __builtin_amdgcn_readlane(W.b_c3x, a),
-                                     __builtin_amdgcn_readlane(W.b_so, a),
-                                     __builtin_amdgcn_readlane(W.b_sox, a),
+              attempt<G, kLds, kTbl>(W, __builtin_amdgcn_readlane(lo(W.b_ku), a),
+                                     __builtin_amdgcn_readlane(hi(W.b_ku), a),
+                                     __builtin_amdgcn_readlane(lo(W.b_c2p), a),
+                                     __builtin_amdgcn_readlane(hi(W.b_c2p), a),
+                                     __builtin_amdgcn_readlane(lo(W.b_c3p), a),
+                                     __builtin_amdgcn_readlane(hi(W.b_c3p), a),
+                                     __builtin_amdgcn_readlane(lo(W.b_sop), a),
+                                     __builtin_amdgcn_readlane(hi(W.b_sop), a),
                                      W.t + (uint64_t)a);
             }
           }
