@@ -154,7 +154,10 @@ int build_coop(muca_ctx c, int which) {
     const GroupDesc& g = c->g[i];
     for (int f = 0; f < g.walkers; f += wpb)
       per[i].push_back(SweepTask{i, g.first_walker + f, std::min(wpb, g.walkers - f), 0});
-    need = std::max(need, (size_t)wpb * (size_t)(g.words + 2 * g.N) * sizeof(uint32_t));
+    // per walker: (site, coordinates) pairs, bits rounded up to whole pairs;
+    // one word of alignment slack before the first slot
+    need = std::max(need, (size_t)wpb * (size_t)(2 * g.N + ((g.words + 1) & ~1)) *
+                              sizeof(uint32_t) + sizeof(uint32_t));
     c->hist_bytes = std::max(c->hist_bytes, (size_t)g.nbins * sizeof(int32_t));
   }
   std::vector<SweepTask> sets;

@@ -172,8 +172,8 @@ template <int G, bool kLds, bool kTbl>
 struct Walker {
   const GroupDesc* g;
   uint32_t* bits;
-  uint32_t* plin;
-  uint32_t* pxyz;  // LDS mode only
+  uint32_t* plin;  // particle sites (device-memory mode)
+  uint64_t* pp;    // LDS mode: (site, packed coordinates) of every particle
   const uint32_t* th;  // threshold table (LDS copy or device memory)
   int32_t* hist;
   int ls, base, d2, nd;
@@ -207,14 +207,15 @@ __device__ __forceinline__ void batch_phase(Walker<G, kLds, kTbl>& W, uint64_t t
   const U4 r = philox((uint32_t)tl, (uint32_t)(tl >> 32), 0u, 0u, W.key0, W.seed32);
   const uint32_t k = draw(r.x, W.N);
   const uint32_t c2 = draw(r.z, W.V), c3 = draw(r.w, W.V);
-  const uint32_t so = ld<kLds>(&W.plin[k]);
-  uint32_t sox;
-  if constexpr (kLds) sox = W.pxyz[k];
-  else sox = site_xyz(g, so);
   W.b_ku = pair(k, r.y);
   W.b_c2p = pair(c2, site_xyz(g, c2));
   W.b_c3p = pair(c3, site_xyz(g, c3));
-  W.b_sop = pair(so, sox);
+  if constexpr (kLds) {
+    W.b_sop = W.pp[k];
+  } else {
+    const uint32_t so = ld<kLds>(&W.plin[k]);
+    W.b_sop = pair(so, site_xyz(g, so));
+  }
 }
 
 // This lane's site in the main gather of an attempt and its bit location.
@@ -287,8 +288,8 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
   const int dE = ko - kn;
   const bool acc = (ok >> (W.base + dE + d2)) & 1u;
   if (acc && W.ls == 0) {
-    st<kLds>(&W.plin[k], sn);
-    if constexpr (kLds) W.pxyz[k] = snx;
+    if constexpr (kLds) W.pp[k] = pair(sn, snx);
+    else st<kLds>(&W.plin[k], sn);
     flip<kLds>(g, W.bits, so, sox, sn, snx);
   }
   if constexpr (!kLds) {
@@ -462,22 +463,23 @@ __device__ __forceinline__ void run_set(
   int32_t* lhist = reinterpret_cast<int32_t*>(smem + tbl_words);
   if constexpr (kLds) {
     for (int i = threadIdx.x; i < g.nbins; i += blockDim.x) lhist[i] = 0;
-    W.bits = smem + (size_t)tbl_words + (size_t)hist_words +
-             (size_t)slot * (size_t)(g.words + 2 * g.N);
-    W.plin = W.bits + g.words;
-    W.pxyz = W.plin + g.N;
+    // walker slots start 8-byte aligned: (site, coordinates) pairs, then bits
+    uint32_t* state = smem + (((size_t)tbl_words + (size_t)hist_words + 1) & ~(size_t)1);
+    const size_t stride = 2 * (size_t)g.N + (((size_t)g.words + 1) & ~(size_t)1);
+    W.pp = reinterpret_cast<uint64_t*>(state + (size_t)slot * stride);
+    W.bits = state + (size_t)slot * stride + 2 * (size_t)g.N;
+    W.plin = nullptr;
     if (has) {
       for (int i = W.ls; i < g.words; i += G) W.bits[i] = sb[i];
       for (int i = W.ls; i < g.N; i += G) {
         const uint32_t s = sp[i];
-        W.plin[i] = s;
-        W.pxyz[i] = site_xyz(g, s);
+        W.pp[i] = pair(s, site_xyz(g, s));
       }
     }
   } else {
     W.bits = sb;
     W.plin = sp;
-    W.pxyz = nullptr;
+    W.pp = nullptr;
   }
   __syncthreads();
 
@@ -573,7 +575,7 @@ __device__ __forceinline__ void run_set(
     __syncthreads();
     if (has) {
       for (int i = W.ls; i < g.words; i += G) sb[i] = W.bits[i];
-      for (int i = W.ls; i < g.N; i += G) sp[i] = W.plin[i];
+      for (int i = W.ls; i < g.N; i += G) sp[i] = lo(W.pp[i]);
     }
     for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
       if (lhist[i]) atomicAdd(&H[g.bin_off + i], lhist[i]);
