@@ -372,6 +372,44 @@ def test_full_size_sampled_walkers(name, sample, variant):
         assert np.array_equal(bits_to_occ(bits, len(n)), n)
 
 
+def recount_energy(occ, d, L):
+    """E = -(occupied nearest-neighbour pairs), periodic (site s = x + L y + L^2 z)."""
+    n = occ.reshape((L,) * d).astype(np.int64)
+    return -int(sum((n * np.roll(n, 1, axis=a)).sum() for a in range(d)))
+
+
+@pytest.mark.parametrize("variant", [None, VARIANTS[1], VARIANTS[2], VARIANTS[8]],
+                         ids=["auto", VARIANT_IDS[1], VARIANT_IDS[2], VARIANT_IDS[8]])
+@pytest.mark.parametrize("name", ["batched_2d", "cubic_3d", "batched_3d", "large_3d"])
+def test_full_size_invariants(name, variant):
+    """Invariants of the walker state after a sweep of the full population:
+    N occupied sites, the particle list on occupied sites and distinct, the
+    incremental energy equal to a recount, inside the window; sum of H equal
+    to walkers x sweeps per group."""
+    wl = W.WORKLOADS[name]
+    groups = wl["groups"]
+    say("invariants", name, variant)
+    ctx = make_ctx(groups, wl["seed"], variant)
+    lnW = W.random_lnW(ctx.total_bins, seed=21, scale=0.3)
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+    ctx.sweep(dev_f64(lnW), 2, H)
+    Hn = H.cpu().numpy()
+    rng = np.random.default_rng(5)
+    first = 0
+    for g, (d, L, N, walkers, *_r) in enumerate(groups):
+        lo, hi, off = ctx.window(g)
+        assert Hn[off:off + hi - lo + 1].sum() == walkers * 2
+        for w in first + rng.choice(walkers, size=min(walkers, 3), replace=False):
+            bits, pos, E, t = ctx.read_walker(int(w))
+            occ = bits_to_occ(bits, L ** d)
+            pos = np.array(pos, dtype=np.int64)
+            assert occ.sum() == N and len(np.unique(pos)) == N
+            assert occ[pos].all()
+            assert E == recount_energy(occ, d, L) and lo <= E <= hi
+            assert t == 2 * L ** d
+        first += walkers
+
+
 def test_errors():
     ctx = M.Context([(2, 8, 16, 4)], seed=1)
     lnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device=DEV)
