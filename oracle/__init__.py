@@ -52,7 +52,8 @@ def lib():
         "ref_update": (ctypes.c_int, [vp, i32p, f64p, f64p, ctypes.c_int, i32p]),
         "ref_flat": (ctypes.c_int, [vp, i32p, i32p]),
         "ref_run": (ctypes.c_int, [vp, f64p, f64p, i32p, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_int, ctypes.c_int, i32p, i32p]),
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p, i32p]),
+        "ref_get_tunnel": (ctypes.c_int, [vp, u32p, u32p]),
         "ref_get_walker": (ctypes.c_int, [vp, ctypes.c_int, u8p, u32p, i32p, u64p]),
         "ref_set_walker": (ctypes.c_int, [vp, ctypes.c_int, u8p, u32p, ctypes.c_int32,
                                           ctypes.c_uint64]),
@@ -179,14 +180,16 @@ class RefContext:
         lib().ref_flat(self._h, _ptr(H, ctypes.c_int32), _ptr(f, ctypes.c_int32))
         return f
 
-    def run(self, lnW, P, sweeps, max_iters, rule=0, stop_on_flat=False):
-        """In-place run; returns (status, H, iters, flat)."""
+    def run(self, lnW, P, sweeps, max_iters, rule=0, stop_on_flat=False, tunnel_target=None):
+        """In-place run; returns (status, H, iters, flat).  With tunnel_target a
+        group stops once its walkers made that many tunnelling events."""
         H = np.zeros(self.total_bins, dtype=np.int32)
         it = np.zeros(self.ngroups, dtype=np.int32)
         fl = np.zeros(self.ngroups, dtype=np.int32)
+        stop = 2 if tunnel_target is not None else (1 if stop_on_flat else 0)
         rc = lib().ref_run(self._h, _ptr(lnW, ctypes.c_double), _ptr(P, ctypes.c_double),
                            _ptr(H, ctypes.c_int32), int(sweeps), int(max_iters), int(rule),
-                           1 if stop_on_flat else 0, _ptr(it, ctypes.c_int32),
+                           stop, int(tunnel_target or 0), _ptr(it, ctypes.c_int32),
                            _ptr(fl, ctypes.c_int32))
         if rc < 0:
             raise RuntimeError(f"ref_run failed ({rc})")
@@ -217,6 +220,13 @@ class RefContext:
         pos = np.ascontiguousarray(pos, dtype=np.uint32)
         lib().ref_set_walker(self._h, w, _ptr(n, ctypes.c_uint8), _ptr(pos, ctypes.c_uint32),
                              int(E), int(t))
+
+    def tunnel(self):
+        """(last window end visited, tunnelling events) per walker, uint32 arrays."""
+        last = np.zeros(self.nwalkers, dtype=np.uint32)
+        trips = np.zeros(self.nwalkers, dtype=np.uint32)
+        lib().ref_get_tunnel(self._h, _ptr(last, ctypes.c_uint32), _ptr(trips, ctypes.c_uint32))
+        return last, trips
 
     def recount(self, w):
         return int(lib().ref_recount(self._h, w))

@@ -273,6 +273,8 @@ typedef struct {
   uint32_t* pos;  /* site of every particle */
   int32_t E;
   uint64_t t;     /* attempts made so far */
+  uint32_t last_end;  /* window end visited last: 0 none yet, 1 bottom, 2 top */
+  uint32_t trips;     /* tunnelling events completed (see tunnel_visit) */
 } walker;
 
 struct ref_ctx {
@@ -397,6 +399,14 @@ int ref_get_walker(const ref_ctx* c, int wi, uint8_t* n, uint32_t* pos, int32_t*
   return 0;
 }
 
+int ref_get_tunnel(const ref_ctx* c, uint32_t* last_end, uint32_t* trips) {
+  for (int i = 0; i < c->nwalkers; ++i) {
+    if (last_end) last_end[i] = c->w[i].last_end;
+    if (trips) trips[i] = c->w[i].trips;
+  }
+  return 0;
+}
+
 int ref_set_walker(ref_ctx* c, int wi, const uint8_t* n, const uint32_t* pos, int32_t E,
                    uint64_t t) {
   if (wi < 0 || wi >= c->nwalkers) return -1;
@@ -462,6 +472,21 @@ static void attempt(walker* w, const ref_group* g, const double* lnW, uint32_t s
   w->t += 1;
 }
 
+/* Sec. 4: the paper counts convergence in tunnelling events, a walker
+ * travelling from the top of the energy range to its bottom or back.  The
+ * walker's energy is looked at once per sweep, where its histogram entry is
+ * taken: standing at the window's bottom (e_lo) or top (e_hi) after last
+ * touching the other end completes one trip.  (A window of one bin has
+ * no trips.) */
+static void tunnel_visit(walker* w, const ref_group* g) {
+  int end = 0;
+  if (w->E == g->e_lo) end = 1;
+  else if (w->E == g->e_hi) end = 2;
+  if (end == 0 || (uint32_t)end == w->last_end) return;
+  if (w->last_end != 0) w->trips += 1;
+  w->last_end = (uint32_t)end;
+}
+
 /* Sec. 2, eq. (2): every process j samples H^i_j(E) with the same weights
  * W^i; the histograms are summed, H^i(E) = sum_j H^i_j(E).  Here each walker
  * plays the role of one process.  A sweep is L^d updates (Sec. 4); the
@@ -482,6 +507,7 @@ int ref_sweep(ref_ctx* c, const double* lnW, int sweeps, int32_t* H, const int32
       for (int s = 0; s < sweeps; ++s) {
         for (int64_t a = 0; a < V; ++a) attempt(w, g, lw, c->seed32);
         Hg[w->E - g->e_lo] += 1;
+        tunnel_visit(w, g);
       }
     }
   }
@@ -569,15 +595,25 @@ int ref_flat(const ref_ctx* c, const int32_t* H, int32_t* flags) {
   return 0;
 }
 
+/* Tunnelling events of group gi so far: the sum of its walkers' trips. */
+static int64_t group_trips(const ref_ctx* c, int gi) {
+  int64_t n = 0;
+  for (int j = 0; j < c->g[gi].walkers; ++j) n += c->w[c->first_walker[gi] + j].trips;
+  return n;
+}
+
 /* The iteration of Sec. 2: equilibrium runs with fixed weights W^i, summed
  * histogram H^i, new weights W^{i+1}; repeated until converged.
- * stop_on_flat = 0: exactly max_iters iterations of (sweep, update); returns
+ * stop = 0: exactly max_iters iterations of (sweep, update); returns
  *   lnW^K, H^{K-1}; flat[g] reports the last histogram.
- * stop_on_flat = 1: a group stops at its first flat H^i; it keeps lnW^i and
- *   H^i and iters[g] = i + 1.  Groups still running after max_iters hold
- *   lnW^{max_iters}, H^{max_iters-1}; the return value is then 1. */
+ * stop = 1: a group stops at its first flat H^i; it keeps lnW^i and H^i and
+ *   iters[g] = i + 1.  Groups still running after max_iters hold
+ *   lnW^{max_iters}, H^{max_iters-1}; the return value is then 1.
+ * stop = 2 (Sec. 4): as 1, but a group stops once its walkers have made
+ *   tunnel_target tunnelling events in total (counted since the walkers
+ *   were created, at the end of each iteration's sweeps). */
 int ref_run(ref_ctx* c, double* lnW, double* P, int32_t* H, int sweeps, int max_iters,
-            int rule, int stop_on_flat, int32_t* iters, int32_t* flat) {
+            int rule, int stop, int tunnel_target, int32_t* iters, int32_t* flat) {
   int G = c->ngroups;
   int32_t* active = (int32_t*)malloc(sizeof(int32_t) * (size_t)G);
   int32_t* f = (int32_t*)malloc(sizeof(int32_t) * (size_t)G);
@@ -595,7 +631,7 @@ int ref_run(ref_ctx* c, double* lnW, double* P, int32_t* H, int sweeps, int max_
       if (!active[g]) continue;
       iters[g] = i + 1;
       flat[g] = f[g];
-      if (stop_on_flat && f[g]) {
+      if ((stop == 1 && f[g]) || (stop == 2 && group_trips(c, g) >= tunnel_target)) {
         active[g] = 0;
         --remaining;
       }
@@ -604,7 +640,7 @@ int ref_run(ref_ctx* c, double* lnW, double* P, int32_t* H, int sweeps, int max_
     rc = ref_update(c, H, lnW, P, rule, active);
     if (rc) { status = rc; goto done; }
   }
-  if (stop_on_flat && remaining > 0) status = 1;
+  if (stop && remaining > 0) status = 1;
 done:
   free(active);
   free(f);

@@ -76,11 +76,16 @@ int ref_update(ref_ctx* c, const int32_t* H, double* lnW, double* P, int rule,
                const int32_t* active);
 /* flags[g] = 1 if the histogram of group g is flat. */
 int ref_flat(const ref_ctx* c, const int32_t* H, int32_t* flags);
-/* Whole iteration loop (see muca_ref.c).  Returns 0 when every group is
- * flat (stop_on_flat) or the fixed count is done, 1 when max_iters is hit
- * before flatness, <0 on error. */
+/* Whole iteration loop (see muca_ref.c).  stop: 0 fixed count, 1 until
+ * flat, 2 until tunnel_target tunnelling events per group.  Returns 0 when
+ * every group has stopped or the fixed count is done, 1 when max_iters is
+ * hit first, <0 on error. */
 int ref_run(ref_ctx* c, double* lnW, double* P, int32_t* H, int sweeps, int max_iters,
-            int rule, int stop_on_flat, int32_t* iters, int32_t* flat);
+            int rule, int stop, int tunnel_target, int32_t* iters, int32_t* flat);
+/* Per walker: the window end visited last (0 none, 1 bottom, 2 top, looked at
+ * after every sweep) and the tunnelling events (trips from one end to the
+ * other) completed since creation.  Either array may be NULL. */
+int ref_get_tunnel(const ref_ctx* c, uint32_t* last_end, uint32_t* trips);
 
 /* Walker state access (occupation bytes n[V], particle sites pos[N]). */
 int ref_get_walker(const ref_ctx* c, int w, uint8_t* n, uint32_t* pos, int32_t* E,
