@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 #define MUCA_OK 0
-#define MUCA_NOT_CONVERGED 1  /* mucaRun: max_iters reached before every group was flat */
+#define MUCA_NOT_CONVERGED 1  /* mucaRun: max_iters reached before every group stopped */
 #define MUCA_EINVAL (-1)      /* invalid argument */
 #define MUCA_EOVERFLOW (-2)   /* walkers x sweeps of a group exceeds INT32_MAX */
 #define MUCA_ENOMEM (-3)      /* device allocation failed */
@@ -58,6 +58,11 @@ extern "C" {
 
 #define MUCA_RULE_BERG 0   /* recursive scheme of Sec. 2, read as Berg's error-weighted recursion */
 #define MUCA_RULE_SIMPLE 1 /* W^{i+1}(E) = W^i(E) / H^i(E), Sec. 2 */
+
+#define MUCA_STOP_NONE 0    /* mucaRun: a fixed number of iterations */
+#define MUCA_STOP_FLAT 1    /* mucaRun: a group stops at its first flat histogram */
+#define MUCA_STOP_TUNNEL 2  /* mucaRun: a group stops once its walkers made the
+                               tunnelling target (mucaSetTunnelTarget), Sec. 4 */
 
 #define MUCA_LAYOUT_AUTO 0  /* chosen per context (see mucaAutotune) */
 #define MUCA_LAYOUT_LANE 1  /* one walker per lane, walker state in device memory */
@@ -199,19 +204,39 @@ int mucaIsFlat(muca_ctx ctx, const int32_t* H, int32_t* flags, void* stream);
  * groups, iteration count continued), so a long run can be split into
  * several calls; max_iters then counts the iterations of this call.
  * iters and flat are host arrays of ngroups int32.
- *   stop_on_flat = 0: exactly max_iters iterations of (sweep, update):
+ *   stop = MUCA_STOP_NONE: exactly max_iters iterations of (sweep, update):
  *     lnW = lnW^K, H = H^{K-1}, flat[g] = flatness of H^{K-1}, iters[g] = K.
- *   stop_on_flat = 1: group g stops at its first flat H^i: lnW keeps lnW^i,
- *     H keeps H^i, iters[g] = i + 1, flat[g] = 1.  Groups not flat after
- *     max_iters keep lnW^{max_iters}, H^{max_iters - 1}, flat[g] = 0, and the
- *     call returns MUCA_NOT_CONVERGED.
+ *   stop = MUCA_STOP_FLAT: group g stops at its first flat H^i: lnW keeps
+ *     lnW^i, H keeps H^i, iters[g] = i + 1, flat[g] = 1.  Groups not flat
+ *     after max_iters keep lnW^{max_iters}, H^{max_iters - 1}, flat[g] = 0,
+ *     and the call returns MUCA_NOT_CONVERGED.
+ *   stop = MUCA_STOP_TUNNEL (the criterion of Sec. 4): as MUCA_STOP_FLAT, but
+ *     group g stops after the first iteration i at whose end its walkers
+ *     have made the tunnelling target in total (see mucaGetTunnel; counted
+ *     since the context was created); flat[g] reports H^i.
+ * Any other stop value is MUCA_EINVAL.
  * The per-iteration work (thresholds, sweep, loop control, recursion) is
  * captured once as a HIP graph on an internal stream, ordered after the
  * caller's stream, and replayed; the graph is kept for later calls with the
  * same pointers and parameters. */
 int mucaRun(muca_ctx ctx, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
-            int max_iters, int rule, int stop_on_flat, int resume, int32_t* iters,
+            int max_iters, int rule, int stop, int resume, int32_t* iters,
             int32_t* flat, void* stream);
+
+/* Tunnelling events (Sec. 4 measures convergence by them: trips of a walker
+ * from the top of its group's energy window to the bottom or back).  A
+ * walker's energy is looked at after every sweep, where its histogram entry
+ * is taken: at e_lo or e_hi after last visiting the other end it completes
+ * a trip.  A window of one bin has no trips.  The counts run from the
+ * context's creation, through every mucaSweep and mucaRun (mucaAutotune
+ * restores them).
+ * mucaSetTunnelTarget: trips per group that end a MUCA_STOP_TUNNEL run
+ *   (target >= 1; 30 when never set, as in Sec. 4).
+ * mucaGetTunnel: per walker (host arrays of nwalkers uint32, either may be
+ *   NULL; waits for the device) the end visited last (0 none yet, 1 e_lo,
+ *   2 e_hi) and the trips completed. */
+int mucaSetTunnelTarget(muca_ctx ctx, int target);
+int mucaGetTunnel(muca_ctx ctx, uint32_t* last_end, uint32_t* trips);
 
 /* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's
  * stream instead of replaying the captured graph (same results). */

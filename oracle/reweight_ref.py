@@ -1,0 +1,47 @@
+"""Reference of the canonical reweighting after the weight iteration.
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Plain numpy in binary64, written
+from the definitions.  Sec. 3 states the motivation: the multicanonical run
+drives the system between the evaporated and the condensed phase and the
+results are reweighted to the relevant temperatures afterwards.
+
+A run with weights W(E) visits energy E with probability proportional to
+Omega(E) W(E), so its histogram H(E) estimates the density of states up to
+a constant: ln Omega(E) = ln H(E) - ln W(E) on the visited bins (bins with
+H(E) = 0 carry no estimate and are left out).  The canonical distribution at
+inverse temperature beta (J = 1, k_B = 1) is P_beta(E) proportional to
+Omega(E) exp(-beta E); from it
+    ln Z(beta)  = ln sum_E exp(ln Omega(E) - beta E)   (same constant as ln Omega),
+    <E>         = sum_E E P_beta(E),
+    <E^2>       = sum_E E^2 P_beta(E),
+    C(beta)     = beta^2 sum_E (E - <E>)^2 P_beta(E)   (specific heat, total).
+The sums are shifted by the largest exponent before exp; the variance is
+taken about the mean (two passes), not as <E^2> - <E>^2.
+"""
+import numpy as np
+
+
+def reweight(lnW, H, e_lo, betas):
+    """One group: lnW[b], H[b] for E = e_lo + b.  Returns an array of shape
+    (len(betas), 4): ln Z, <E>, <E^2>, C per beta (NaN when no bin is
+    visited)."""
+    lnW = np.asarray(lnW, dtype=np.float64)
+    H = np.asarray(H, dtype=np.int64)
+    E = e_lo + np.arange(len(H), dtype=np.float64)
+    seen = H > 0
+    out = np.full((len(betas), 4), np.nan)
+    if not seen.any():
+        return out
+    ln_omega = np.log(H[seen].astype(np.float64)) - lnW[seen]
+    Es = E[seen]
+    for k, beta in enumerate(betas):
+        a = ln_omega - beta * Es
+        m = a.max()
+        w = np.exp(a - m)
+        z = w.sum()
+        mean = (w * Es).sum() / z
+        out[k, 0] = m + np.log(z)
+        out[k, 1] = mean
+        out[k, 2] = (w * Es * Es).sum() / z
+        out[k, 3] = beta * beta * (w * (Es - mean) ** 2).sum() / z
+    return out

@@ -30,6 +30,7 @@ struct muca_context {
   uint32_t* d_pos = nullptr;
   int32_t* d_E = nullptr;
   uint64_t* d_T = nullptr;
+  uint32_t* d_tun = nullptr;  // per walker: last window end (bits 0-1), trips (bits 2-31)
   int32_t* d_wgroup = nullptr;
   uint32_t* d_thr = nullptr;
   double* d_slope = nullptr;
@@ -40,6 +41,7 @@ struct muca_context {
   int32_t* d_iters = nullptr;
   int32_t* d_counter = nullptr;  // [0] iteration index, [1] groups still active
   int32_t* h_pinned = nullptr;   // host-pinned readback of the counters
+  int tunnel_target = 30;        // trips per group that end a MUCA_STOP_TUNNEL run
   int layout = MUCA_LAYOUT_AUTO;  // requested
   int tuned = 0;                  // layout picked by mucaAutotune (0 = none yet)
   hipStream_t last_stream = nullptr;
@@ -65,11 +67,12 @@ struct muca_context {
   hipGraphExec_t graph_exec = nullptr;
   struct GraphKey {
     const void *lnW, *P, *H;
-    int sweeps, rule, stop, layout;
+    int sweeps, rule, stop, layout, tunnel_target;
     size_t lds_limit;
     bool operator==(const GraphKey& o) const {
       return lnW == o.lnW && P == o.P && H == o.H && sweeps == o.sweeps && rule == o.rule &&
-             stop == o.stop && layout == o.layout && lds_limit == o.lds_limit;
+             stop == o.stop && layout == o.layout && tunnel_target == o.tunnel_target &&
+             lds_limit == o.lds_limit;
     }
   } graph_key{};
   size_t lds_limit = kLdsBytes;  // LDS a cooperative block may use
@@ -81,6 +84,7 @@ struct muca_context {
     (void)hipFree(d_pos);
     (void)hipFree(d_E);
     (void)hipFree(d_T);
+    (void)hipFree(d_tun);
     (void)hipFree(d_wgroup);
     (void)hipFree(d_thr);
     (void)hipFree(d_slope);

@@ -249,4 +249,18 @@ __device__ __forceinline__ bool accepts(uint32_t T, uint32_t u) {
   return (T == kAlways) | (u < T);
 }
 
+// ---------------------------------------------------------------- tunnelling
+// Sec. 4 counts convergence in tunnelling events: trips of a walker from the
+// top of the energy window to its bottom or back.  A walker's state packs
+// the window end it visited last (bits 0-1: 0 none yet, 1 bottom, 2 top) and
+// its completed trips (bits 2-31).  It is updated once per sweep, where the
+// histogram entry is taken, with the walker's bin b (0 = e_lo, top = e_hi).
+// A window of one bin never completes a trip.
+__device__ __forceinline__ uint32_t tunnel_step(uint32_t st, int32_t b, int32_t top) {
+  const uint32_t end = b == 0 ? 1u : (b == top ? 2u : 0u);
+  const uint32_t last = st & 3u;
+  if (end == 0u || end == last) return st;
+  return ((st & ~3u) + (last != 0u ? 4u : 0u)) | end;
+}
+
 }  // namespace muca

@@ -97,9 +97,9 @@ __global__ void k_zero_hist(const GroupDesc* __restrict__ groups, const int32_t*
 __global__ void __launch_bounds__(64) k_sweep_lane(
     const GroupDesc* __restrict__ groups, const int32_t* __restrict__ wgroup,
     uint32_t* __restrict__ bits, uint32_t* __restrict__ pos, int32_t* __restrict__ E,
-    uint64_t* __restrict__ T, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
-    const int32_t* __restrict__ active, int nwalkers, int sweeps, uint32_t first_id,
-    uint32_t seed32) {
+    uint64_t* __restrict__ T, uint32_t* __restrict__ tun, const uint32_t* __restrict__ thr,
+    int32_t* __restrict__ H, const int32_t* __restrict__ active, int nwalkers, int sweeps,
+    uint32_t first_id, uint32_t seed32) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nwalkers) return;
   const int gi = wgroup[w];
@@ -113,6 +113,7 @@ __global__ void __launch_bounds__(64) k_sweep_lane(
   const uint32_t key0 = first_id + (uint32_t)w;
   int32_t e = E[w];
   uint64_t t = T[w];
+  uint32_t tn = tun[w];
   const uint32_t V = (uint32_t)g.V, N = (uint32_t)g.N;
   for (int sw = 0; sw < sweeps; ++sw) {
     for (uint32_t a = 0; a < V; ++a, ++t) {
@@ -154,9 +155,11 @@ __global__ void __launch_bounds__(64) k_sweep_lane(
       }
     }
     atomicAdd(&hg[e - g.e_lo], 1);
+    tn = tunnel_step(tn, e - g.e_lo, g.nbins - 1);
   }
   E[w] = e;
   T[w] = t;
+  tun[w] = tn;
 }
 
 // ---------------------------------------------------------------- recursion
@@ -277,8 +280,10 @@ __global__ void __launch_bounds__(256) k_flat(const GroupDesc* __restrict__ grou
 }
 
 // Loop control of the iteration: for each active group record the flatness
-// of H^i and the iteration count; with stop_on_flat a flat group becomes
-// inactive (keeps lnW^i, H^i).  remaining = number of groups still active.
+// of H^i and the iteration count.  stop = 1: a flat group becomes inactive
+// (keeps lnW^i, H^i); stop = 2: so does a group whose walkers have made
+// tunnel_target tunnelling events in total (Sec. 4).  remaining = number of
+// groups still active.
 __global__ void __launch_bounds__(256) k_control(const GroupDesc* __restrict__ groups,
                                                  const int32_t* __restrict__ H,
                                                  int32_t* __restrict__ active,
@@ -286,21 +291,30 @@ __global__ void __launch_bounds__(256) k_control(const GroupDesc* __restrict__ g
                                                  int32_t* __restrict__ iters,
                                                  int32_t* __restrict__ iter_counter,
                                                  int32_t* __restrict__ remaining,
-                                                 int stop_on_flat) {
+                                                 const uint32_t* __restrict__ tun, int stop,
+                                                 int tunnel_target) {
   const int gi = blockIdx.x;
   if (!active[gi]) return;
   const GroupDesc g = groups[gi];
   __shared__ int mn_s, mx_s;
+  __shared__ unsigned long long trips_s;
   if (threadIdx.x == 0) {
     mn_s = 0x7FFFFFFF;
     mx_s = 0;
+    trips_s = 0ull;
   }
   __syncthreads();
   const int f = group_flat(H + g.bin_off, g.nbins, &mn_s, &mx_s);
+  if (stop == 2) {
+    unsigned long long n = 0ull;
+    for (int j = threadIdx.x; j < g.walkers; j += blockDim.x) n += tun[g.first_walker + j] >> 2;
+    atomicAdd(&trips_s, n);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     flat[gi] = f;
     iters[gi] = *iter_counter + 1;
-    if (stop_on_flat && f) {
+    if ((stop == 1 && f) || (stop == 2 && trips_s >= (unsigned long long)tunnel_target)) {
       active[gi] = 0;
       atomicSub(remaining, 1);
     }

@@ -242,7 +242,8 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
                         : (tbl_lds ? muca::k_sweep_sub<64, false, true, false>
                                    : muca::k_sweep_sub<64, false, false, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
-                     q.d_first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active,
+                     q.d_first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, c->d_thr, H,
+                     active,
                      sweeps, c->first_id, c->seed32, tbl_words,
                      state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0, kCoopSpread[which]);
   LAUNCH_CHECK();
@@ -261,7 +262,7 @@ int launch_look(muca_ctx c, int sweeps, int32_t* H, const int32_t* active, hipSt
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
   auto kern = tbl_lds ? muca::k_sweep_look<true> : muca::k_sweep_look<false>;
   hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
-                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_thr, H, active, sweeps,
+                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, c->d_thr, H, active, sweeps,
                      c->first_id, c->seed32, tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0,
                      (int)(c->hist_bytes / sizeof(int32_t)));
   LAUNCH_CHECK();
@@ -274,7 +275,8 @@ int enqueue_sweep_kernel(muca_ctx c, int layout, int sweeps, int32_t* H, const i
     case MUCA_LAYOUT_LANE:
       hipLaunchKernelGGL(muca::k_sweep_lane, dim3((unsigned)((c->nwalkers + 63) / 64)), dim3(64),
                          0, s, c->d_groups, c->d_wgroup, c->d_bits, c->d_pos, c->d_E, c->d_T,
-                         c->d_thr, H, active, c->nwalkers, sweeps, c->first_id, c->seed32);
+                         c->d_tun, c->d_thr, H, active, c->nwalkers, sweeps, c->first_id,
+                         c->seed32);
       LAUNCH_CHECK();
       return MUCA_OK;
     case MUCA_LAYOUT_SUB16:
@@ -431,6 +433,7 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
     if ((r = dev_alloc(&c->d_pos, (size_t)pos))) return r;
     if ((r = dev_alloc(&c->d_E, (size_t)walkers))) return r;
     if ((r = dev_alloc(&c->d_T, (size_t)walkers))) return r;
+    if ((r = dev_alloc(&c->d_tun, (size_t)walkers))) return r;
     if ((r = dev_alloc(&c->d_wgroup, (size_t)walkers))) return r;
     if ((r = dev_alloc(&c->d_thr, (size_t)thr))) return r;
     if ((r = dev_alloc(&c->d_slope, (size_t)bins))) return r;
@@ -445,6 +448,7 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_wgroup, wg.data(), sizeof(int32_t) * wg.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(c->d_status, 0, sizeof(int32_t)));
+    HIP_TRY(hipMemset(c->d_tun, 0, sizeof(uint32_t) * (size_t)walkers));
     hipLaunchKernelGGL(muca::k_fill_i32, dim3(1), dim3(256), 0, nullptr, c->d_ones, 1, ngroups);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(muca::k_init_place, dim3((unsigned)((walkers + 63) / 64)), dim3(64), 0,
@@ -552,6 +556,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
   uint32_t *b0 = nullptr, *p0 = nullptr;
   int32_t *e0 = nullptr, *h = nullptr;
   uint64_t* t0 = nullptr;
+  uint32_t* u0 = nullptr;
   int rc = MUCA_OK;
   double best = 1e300;
   int pick = MUCA_LAYOUT_SUB16;
@@ -566,6 +571,8 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
                            sizeof(int32_t) * (size_t)c->nwalkers, k, s));
     HIP_TRY(hipMemcpyAsync(back ? c->d_T : t0, back ? t0 : c->d_T,
                            sizeof(uint64_t) * (size_t)c->nwalkers, k, s));
+    HIP_TRY(hipMemcpyAsync(back ? c->d_tun : u0, back ? u0 : c->d_tun,
+                           sizeof(uint32_t) * (size_t)c->nwalkers, k, s));
     return MUCA_OK;
   };
   auto body = [&]() -> int {
@@ -574,6 +581,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     if ((r = dev_alloc(&p0, (size_t)c->total_pos))) return r;
     if ((r = dev_alloc(&e0, (size_t)c->nwalkers))) return r;
     if ((r = dev_alloc(&t0, (size_t)c->nwalkers))) return r;
+    if ((r = dev_alloc(&u0, (size_t)c->nwalkers))) return r;
     if ((r = dev_alloc(&h, (size_t)c->total_bins))) return r;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
@@ -604,6 +612,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
   (void)hipFree(p0);
   (void)hipFree(e0);
   (void)hipFree(t0);
+  (void)hipFree(u0);
   (void)hipFree(h);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -697,14 +706,15 @@ int mucaStatus(muca_ctx c, void* stream) {
 }
 
 int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter, int max_iters,
-            int rule, int stop_on_flat, int resume, int32_t* iters, int32_t* flat,
-            void* stream) {
+            int rule, int stop, int resume, int32_t* iters, int32_t* flat, void* stream) {
   if (int r = check_ctx(c)) return r;
   if (!lnW || !P || !H || !iters || !flat)
     return fail(MUCA_EINVAL, "lnW, P, H, iters and flat must not be NULL");
   if (max_iters < 1) return fail(MUCA_EINVAL, "max_iters must be >= 1");
   if (rule != MUCA_RULE_BERG && rule != MUCA_RULE_SIMPLE)
     return fail(MUCA_EINVAL, "unknown rule %d", rule);
+  if (stop != MUCA_STOP_NONE && stop != MUCA_STOP_FLAT && stop != MUCA_STOP_TUNNEL)
+    return fail(MUCA_EINVAL, "unknown stop criterion %d", stop);
   if (int r = check_sweeps(c, sweeps_per_iter)) return r;
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
@@ -728,7 +738,7 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
     if (int r = enqueue_sweep(c, lnW, sweeps_per_iter, H, c->d_active, st)) return r;
     hipLaunchKernelGGL(muca::k_control, dim3((unsigned)G), dim3(256), 0, st, c->d_groups, H,
                        c->d_active, c->d_flat, c->d_iters, c->d_counter, c->d_counter + 1,
-                       stop_on_flat);
+                       c->d_tun, stop, c->tunnel_target);
     hipLaunchKernelGGL(muca::k_update, dim3((unsigned)G), dim3(256), 0, st, c->d_groups, H, lnW, P,
                        c->d_slope, rule, c->d_active, c->d_status);
     hipLaunchKernelGGL(muca::k_bump, dim3(1), dim3(64), 0, st, c->d_counter);
@@ -739,8 +749,8 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
   if (c->use_graph) {
     if (!c->run_stream) HIP_TRY(hipStreamCreateWithFlags(&c->run_stream, hipStreamNonBlocking));
     rs = c->run_stream;
-    const muca_context::GraphKey key{lnW, P, H, sweeps_per_iter, rule, stop_on_flat,
-                                     resolved_layout(c), c->lds_limit};
+    const muca_context::GraphKey key{lnW, P, H, sweeps_per_iter, rule, stop, resolved_layout(c),
+                                     c->tunnel_target, c->lds_limit};
     if (!c->graph_exec || !(key == c->graph_key)) {
       if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
       if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -782,7 +792,7 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
     } else if (int r = enqueue_iteration(rs)) {
       return r;
     }
-    if (stop_on_flat) {
+    if (stop != MUCA_STOP_NONE) {
       HIP_TRY(hipMemcpyAsync(c->h_pinned, c->d_counter, 2 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, rs));
       HIP_TRY(hipStreamSynchronize(rs));
@@ -800,7 +810,26 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
   HIP_TRY(hipMemcpyAsync(iters, c->d_iters, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(flat, c->d_flat, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
   if (int r = mucaStatus(c, s)) return r;
-  return (stop_on_flat && remaining > 0) ? MUCA_NOT_CONVERGED : MUCA_OK;
+  return (stop != MUCA_STOP_NONE && remaining > 0) ? MUCA_NOT_CONVERGED : MUCA_OK;
+}
+
+int mucaSetTunnelTarget(muca_ctx c, int target) {
+  if (int r = check_ctx(c)) return r;
+  if (target < 1) return fail(MUCA_EINVAL, "tunnelling target must be >= 1, got %d", target);
+  c->tunnel_target = target;
+  return MUCA_OK;
+}
+
+int mucaGetTunnel(muca_ctx c, uint32_t* last_end, uint32_t* trips) {
+  if (int r = check_ctx(c)) return r;
+  HIP_TRY(hipDeviceSynchronize());
+  std::vector<uint32_t> st((size_t)c->nwalkers);
+  HIP_TRY(hipMemcpy(st.data(), c->d_tun, sizeof(uint32_t) * st.size(), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < st.size(); ++i) {
+    if (last_end) last_end[i] = st[i] & 3u;
+    if (trips) trips[i] = st[i] >> 2;
+  }
+  return MUCA_OK;
 }
 
 int mucaReadWalker(muca_ctx c, int walker, uint32_t* bits, uint32_t* pos, int32_t* E,

@@ -82,6 +82,7 @@ struct Look {
   uint32_t V, N, key0, seed32, in_sweep;
   int32_t E, Ew;  // current energy, energy at which the window was loaded
   uint64_t t;
+  uint32_t tun;  // tunnelling state (see tunnel_step)
   // roles of the fast gather (per row): [0,2d) nbr(s_o), 2d: c2, 2d+1: c3,
   // [2d+2, 4d+2) nbr(c2), [4d+2, 6d+2) nbr(c3) when full
   Role role;
@@ -267,6 +268,7 @@ __device__ __forceinline__ void step(Look& W, int S, int nb) {
       if (W.in_sweep == W.V) {
         W.in_sweep = 0;
         if (W.lane == 0) atomicAdd(&W.hist[W.E - g.e_lo], 1);
+        W.tun = tunnel_step(W.tun, W.E - g.e_lo, g.nbins - 1);
       }
     }
   }
@@ -279,9 +281,9 @@ template <bool kTbl>
 __global__ void __launch_bounds__(256) k_sweep_look(
     const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
-    uint64_t* __restrict__ gT, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
-    const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
-    int tbl_words, int hist_words) {
+    uint64_t* __restrict__ gT, uint32_t* __restrict__ gtun, const uint32_t* __restrict__ thr,
+    int32_t* __restrict__ H, const int32_t* __restrict__ active, int sweeps, uint32_t first_id,
+    uint32_t seed32, int tbl_words, int hist_words) {
   // LDS: [threshold table (tbl_words)] [block histogram (hist_words)] [walker slots]
   extern __shared__ uint32_t smem[];
   const SweepTask task = tasks[blockIdx.x];
@@ -342,6 +344,7 @@ __global__ void __launch_bounds__(256) k_sweep_look(
     W.seed32 = seed32;
     W.E = gE[w];
     W.t = gT[w];
+    W.tun = gtun[w];
     W.in_sweep = 0;
     const int nd = W.nd, nw = nd * nd;
     const int i0 = W.lane, i1 = W.lane + 64, i2 = W.lane + 128;
@@ -362,6 +365,7 @@ __global__ void __launch_bounds__(256) k_sweep_look(
     if (W.lane == 0) {
       gE[w] = W.E;
       gT[w] = W.t;
+      gtun[w] = W.tun;
     }
   }
   __syncthreads();
@@ -374,12 +378,12 @@ __global__ void __launch_bounds__(256) k_sweep_look(
 }
 
 template __global__ void k_sweep_look<true>(const GroupDesc*, const SweepTask*, uint32_t*,
-                                            uint32_t*, int32_t*, uint64_t*, const uint32_t*,
-                                            int32_t*, const int32_t*, int, uint32_t, uint32_t,
-                                            int, int);
+                                            uint32_t*, int32_t*, uint64_t*, uint32_t*,
+                                            const uint32_t*, int32_t*, const int32_t*, int,
+                                            uint32_t, uint32_t, int, int);
 template __global__ void k_sweep_look<false>(const GroupDesc*, const SweepTask*, uint32_t*,
-                                             uint32_t*, int32_t*, uint64_t*, const uint32_t*,
-                                             int32_t*, const int32_t*, int, uint32_t, uint32_t,
-                                             int, int);
+                                             uint32_t*, int32_t*, uint64_t*, uint32_t*,
+                                             const uint32_t*, int32_t*, const int32_t*, int,
+                                             uint32_t, uint32_t, int, int);
 
 }  // namespace muca

@@ -180,6 +180,7 @@ struct Walker {
   uint32_t V, N, key0, seed32;
   int32_t E;  // energy minus the window's e_lo (bin index) during the launch
   uint64_t t;
+  uint32_t tun;  // tunnelling state (see tunnel_step)
   uint32_t Trow;
   // lane roles of the main gather: [0,2d) nbr(s_o), 2d: c2, 2d+1: c3,
   // [2d+2, 4d+2) nbr(c2) and, when 6d+2 lanes are available (full), also
@@ -432,9 +433,9 @@ template <int G, bool kLds, bool kTbl, bool kPipe>
 __device__ __forceinline__ void run_set(
     const GroupDesc* __restrict__ groups, const SweepTask task, uint32_t* smem,
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
-    uint64_t* __restrict__ gT, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
-    const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
-    int tbl_words, int hist_words, int spread) {
+    uint64_t* __restrict__ gT, uint32_t* __restrict__ gtun, const uint32_t* __restrict__ thr,
+    int32_t* __restrict__ H, const int32_t* __restrict__ active, int sweeps, uint32_t first_id,
+    uint32_t seed32, int tbl_words, int hist_words, int spread) {
   if (active && !active[task.group]) return;  // uniform per block
   const GroupDesc g = groups[task.group];
   Walker<G, kLds, kTbl> W;
@@ -504,6 +505,7 @@ __device__ __forceinline__ void run_set(
     W.seed32 = seed32;
     W.E = gE[w] - g.e_lo;
     W.t = gT[w];
+    W.tun = gtun[w];
     W.Trow = (ls < W.nd) ? W.th[W.E * W.nd + ls] : 0u;
     // A batch never straddles the end of a sweep (the last batch of a sweep
     // may be short; its spare lanes compute attempts that the next batch
@@ -531,6 +533,7 @@ __device__ __forceinline__ void run_set(
           W.t += (uint64_t)nb;
         }
         if (ls == 0) atomicAdd(&W.hist[W.E], 1);
+        W.tun = tunnel_step(W.tun, W.E, g.nbins - 1);
       }
     } else {
       W.pm_k = W.pm_so = W.pm_sn = kNone;
@@ -563,11 +566,13 @@ __device__ __forceinline__ void run_set(
           W.t += (uint64_t)nb;
         }
         if (ls == 0) atomicAdd(&W.hist[W.E], 1);
+        W.tun = tunnel_step(W.tun, W.E, g.nbins - 1);
       }
     }
     if (ls == 0) {
       gE[w] = W.E + g.e_lo;
       gT[w] = W.t;
+      gtun[w] = W.tun;
     }
   }
 
@@ -590,7 +595,7 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
     const int32_t* __restrict__ first, uint32_t* __restrict__ gbits,
     uint32_t* __restrict__ gpos, int32_t* __restrict__ gE, uint64_t* __restrict__ gT,
-    const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
+    uint32_t* __restrict__ gtun, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
     const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
     int tbl_words, int hist_words, int spread) {
   static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
@@ -601,34 +606,43 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   const int t0 = first[blockIdx.x], t1 = first[blockIdx.x + 1];
   for (int ti = t0; ti < t1; ++ti) {
     if (ti > t0) __syncthreads();  // the previous set is out of LDS
-    run_set<G, kLds, kTbl, kPipe>(groups, tasks[ti], smem, gbits, gpos, gE, gT, thr, H, active,
-                                  sweeps, first_id, seed32, tbl_words, hist_words, spread);
+    run_set<G, kLds, kTbl, kPipe>(groups, tasks[ti], smem, gbits, gpos, gE, gT, gtun, thr, H,
+                                  active, sweeps, first_id, seed32, tbl_words, hist_words,
+                                  spread);
   }
 }
 
 template __global__ void k_sweep_sub<16, true, true, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<16, true, false, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<16, false, true, true>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<16, false, false, true>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<64, true, true, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<64, true, false, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<64, false, true, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 template __global__ void k_sweep_sub<64, false, false, false>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
-    uint64_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int, int, int);
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
 
 }  // namespace muca

@@ -24,6 +24,9 @@ MUCA_EHIP = -4
 MUCA_ENONFINITE = -5
 MUCA_RULE_BERG = 0
 MUCA_RULE_SIMPLE = 1
+MUCA_STOP_NONE = 0
+MUCA_STOP_FLAT = 1
+MUCA_STOP_TUNNEL = 2
 MUCA_LAYOUT_AUTO = 0
 MUCA_LAYOUT_LANE = 1
 MUCA_LAYOUT_SUB16 = 2
@@ -69,6 +72,8 @@ SIGNATURES = {
     "mucaReadWalker": (ctypes.c_int, [_vp, ctypes.c_int, _P(ctypes.c_uint32),
                                       _P(ctypes.c_uint32), _P(_i32), _P(ctypes.c_uint64)]),
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
+    "mucaSetTunnelTarget": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mucaGetTunnel": (ctypes.c_int, [_vp, _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
     "mucaMlpParamCount": (ctypes.c_int, []),
     "mucaMlpCreate": (ctypes.c_int, [_P(_vp), ctypes.c_int]),
     "mucaMlpDestroy": (ctypes.c_int, [_vp]),
@@ -223,16 +228,28 @@ class Context:
                                 _stream(stream)))
 
     def run(self, lnW, P, H, sweeps, max_iters, rule=MUCA_RULE_BERG, stop_on_flat=False,
-            stream=None, resume=False):
-        """Returns (status, iters[list], flat[list])."""
+            stream=None, resume=False, stop=None):
+        """Returns (status, iters[list], flat[list]).  stop (a MUCA_STOP_*
+        value) overrides stop_on_flat."""
         it = (_i32 * self.ngroups)()
         fl = (_i32 * self.ngroups)()
         rc = _check(lib().mucaRun(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
                                   _dev(P, torch.float64, self.total_bins, "P"),
                                   _dev(H, torch.int32, self.total_bins, "H"), int(sweeps),
-                                  int(max_iters), int(rule), 1 if stop_on_flat else 0,
+                                  int(max_iters), int(rule),
+                                  int(stop) if stop is not None else (1 if stop_on_flat else 0),
                                   1 if resume else 0, it, fl, _stream(stream)))
         return rc, list(it), list(fl)
+
+    def set_tunnel_target(self, target):
+        _check(lib().mucaSetTunnelTarget(self._h, int(target)))
+
+    def tunnel(self):
+        """(last window end visited, tunnelling events) per walker: two lists."""
+        last = (ctypes.c_uint32 * self.nwalkers)()
+        trips = (ctypes.c_uint32 * self.nwalkers)()
+        _check(lib().mucaGetTunnel(self._h, last, trips))
+        return list(last), list(trips)
 
     def status(self, stream=None):
         return _check(lib().mucaStatus(self._h, _stream(stream)))

@@ -41,6 +41,15 @@ def assert_walkers_equal(ctx, ref, walkers):
         assert E == rE and t == rt, (w, E, rE, t, rt)
         assert np.array_equal(bits_to_occ(bits, len(n)), n), w
         assert np.array_equal(np.array(pos, dtype=np.uint32), rpos), w
+    assert_tunnel_equal(ctx, ref)
+
+
+def assert_tunnel_equal(ctx, ref):
+    """Tunnelling state of every walker (last window end, trips), bit-exact."""
+    last, trips = ctx.tunnel()
+    rlast, rtrips = ref.tunnel()
+    assert np.array_equal(np.array(last, dtype=np.uint32), rlast)
+    assert np.array_equal(np.array(trips, dtype=np.uint32), rtrips)
 
 
 def same_f64(a, b):
@@ -236,18 +245,24 @@ def test_sweep_active_mask():
 
 
 def _run_both(groups, seed, sweeps, iters, rule=0, stop_on_flat=False, lnW0=None,
-              check_walkers=True, variant=None):
+              check_walkers=True, variant=None, tunnel_target=None, graph=True):
     say("run", groups, "sweeps", sweeps, "iters", iters, "rule", rule, "flat", stop_on_flat,
-        "variant", variant)
+        "tunnel", tunnel_target, "variant", variant)
     ctx = make_ctx(groups, seed, variant)
+    ctx.set_graph(graph)
+    stop = None
+    if tunnel_target is not None:
+        ctx.set_tunnel_target(tunnel_target)
+        stop = M.MUCA_STOP_TUNNEL
     ref = O.RefContext(groups, seed)
     lnW = np.zeros(ctx.total_bins) if lnW0 is None else np.array(lnW0, dtype=np.float64)
     P = np.full(ctx.total_bins, 123.0)  # mucaRun zeroes P itself
     glnW, gP = dev_f64(lnW), dev_f64(P)
     gH = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
-    rc, it, fl = ctx.run(glnW, gP, gH, sweeps, iters, rule, stop_on_flat)
+    rc, it, fl = ctx.run(glnW, gP, gH, sweeps, iters, rule, stop_on_flat, stop=stop)
     P[:] = 0.0
-    rrc, rH, rit, rfl = ref.run(lnW, P, sweeps, iters, rule, stop_on_flat)
+    rrc, rH, rit, rfl = ref.run(lnW, P, sweeps, iters, rule, stop_on_flat,
+                                tunnel_target=tunnel_target)
     assert rc == rrc
     assert list(it) == list(rit) and list(fl) == list(rfl)
     assert np.array_equal(gH.cpu().numpy(), rH)
@@ -256,6 +271,8 @@ def _run_both(groups, seed, sweeps, iters, rule=0, stop_on_flat=False, lnW0=None
     if check_walkers:
         n = ctx.nwalkers
         assert_walkers_equal(ctx, ref, sorted(set([0, n - 1] + list(range(0, n, max(1, n // 16))))))
+    else:
+        assert_tunnel_equal(ctx, ref)
     return rc, it, fl
 
 
@@ -299,6 +316,40 @@ def test_run_until_flat_per_group(variant):
     # the groups go flat at different iterations (2, 4, 3, 7, 10 for this seed)
     rc, it, fl = _run_both(FLAT_GROUPS, 5, 50, 80, rule=0, stop_on_flat=True, variant=variant)
     assert rc == 0 and all(fl) and len(set(it)) >= 4
+
+
+TUNNEL_GROUPS = [(2, 4, 2, 6, -1, 0), (2, 4, 3, 5), (3, 3, 3, 4), (2, 6, 5, 4, -4, -1),
+                 (3, 6, 12, 3, -10, 0)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_tunnelling_matches_oracle(variant):
+    """Tunnelling state after sweeps with small windows (every layout):
+    last window end and trips of every walker, bit-exact."""
+    say("tunnel", variant)
+    ctx = make_ctx(TUNNEL_GROUPS, 4, variant)
+    ref = O.RefContext(TUNNEL_GROUPS, seed=4)
+    lnW = W.random_lnW(ctx.total_bins, seed=6, scale=0.3)
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+    for call in range(2):  # the state carries over between calls
+        ctx.sweep(dev_f64(lnW), 25, H)
+        rH = ref.sweep(lnW, 25)
+        torch.cuda.synchronize()
+        assert np.array_equal(H.cpu().numpy(), rH), call
+        assert_tunnel_equal(ctx, ref)
+    assert sum(ctx.tunnel()[1]) > 0
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
+@pytest.mark.parametrize("variant", [None, VARIANTS[0], VARIANTS[2], VARIANTS[6], VARIANTS[8]],
+                         ids=["auto", VARIANT_IDS[0], VARIANT_IDS[2], VARIANT_IDS[6],
+                              VARIANT_IDS[8]])
+def test_run_until_tunnelling_target(variant, graph):
+    """The convergence criterion of Sec. 4: each group stops after the first
+    iteration at whose end its walkers made the target number of trips."""
+    rc, it, fl = _run_both(TUNNEL_GROUPS[1:], 9, 10, 200, rule=0, variant=variant,
+                           tunnel_target=12, graph=graph)
+    assert rc == M.MUCA_OK and min(it) >= 1 and len(set(it)) > 1
 
 
 def test_run_until_flat_some_groups_not_converged():
@@ -351,6 +402,7 @@ def test_full_size_sampled_walkers(name, sample, variant):
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
     ctx.sweep(dev_f64(lnW), sweeps, H)
     Hn = H.cpu().numpy()
+    glast, gtrips = ctx.tunnel()
     rng = np.random.default_rng(1)
     first = 0
     picks = []
@@ -368,6 +420,8 @@ def test_full_size_sampled_walkers(name, sample, variant):
         bits, pos, E, t = ctx.read_walker(w)
         n, rpos, rE, rt = ref.walker(0)
         assert (E, t) == (rE, rt), (name, w)
+        rlast, rtrips = ref.tunnel()
+        assert (glast[w], gtrips[w]) == (rlast[0], rtrips[0]), (name, w)
         assert np.array_equal(np.array(pos, dtype=np.uint32), rpos)
         assert np.array_equal(bits_to_occ(bits, len(n)), n)
 
@@ -431,6 +485,12 @@ def test_errors():
     with pytest.raises(M.MucaError) as e:
         ctx.run(bad, P, H, 1, 2)
     assert e.value.code == M.MUCA_ENONFINITE
+    with pytest.raises(M.MucaError) as e:
+        ctx.run(lnW, P, H, 1, 2, stop=3)
+    assert e.value.code == M.MUCA_EINVAL
+    with pytest.raises(M.MucaError) as e:
+        ctx.set_tunnel_target(0)
+    assert e.value.code == M.MUCA_EINVAL
 
 
 def test_determinism_two_contexts():
