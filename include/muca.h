@@ -236,6 +236,23 @@ int mucaRun(muca_ctx ctx, double* lnW, double* P, int32_t* H, int sweeps_per_ite
  *   NULL; waits for the device) the end visited last (0 none yet, 1 e_lo,
  *   2 e_hi) and the trips completed. */
 int mucaSetTunnelTarget(muca_ctx ctx, int target);
+
+/* Canonical reweighting (Sec. 3: the multicanonical data are reweighted to
+ * the temperatures of interest).  H is a histogram taken with weights lnW
+ * (normally a production mucaSweep with the converged weights); both device
+ * arrays in the concatenated bin layout.  beta: device array of nbeta
+ * inverse temperatures (J = 1, k_B = 1).  out: device array of
+ * ngroups x nbeta x 4 doubles, out[(g * nbeta + k) * 4 + j] =
+ *   j = 0: ln Z(beta) = ln sum_E exp(ln Omega(E) - beta E), with
+ *          ln Omega(E) = ln H(E) - lnW(E) over the visited bins (H > 0), so
+ *          up to the same additive constant as ln Omega;
+ *   j = 1: <E>;  j = 2: <E^2>;
+ *   j = 3: C = beta^2 <(E - <E>)^2> (specific heat of the whole lattice).
+ * A group without a visited bin gets NaN.  Sums are shifted by the largest
+ * exponent; binary64 throughout (exp and log of the device math library).
+ * nbeta >= 1, else MUCA_EINVAL; asynchronous on stream. */
+int mucaReweight(muca_ctx ctx, const double* lnW, const int32_t* H, const double* beta,
+                 int nbeta, double* out, void* stream);
 int mucaGetTunnel(muca_ctx ctx, uint32_t* last_end, uint32_t* trips);
 
 /* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's

@@ -321,6 +321,81 @@ __global__ void __launch_bounds__(256) k_control(const GroupDesc* __restrict__ g
   }
 }
 
+// ---------------------------------------------------------------- reweighting
+// Canonical averages from a multicanonical histogram (Sec. 3: the data are
+// reweighted to the temperatures of interest).  A run with weights W visits E
+// with probability ~ Omega(E) W(E), so ln Omega(E) = ln H(E) - ln W(E) on the
+// visited bins, up to a constant.  At inverse temperature beta (J = 1) the
+// canonical weight of E is exp(ln Omega(E) - beta E); with a(E) that exponent
+// and m its largest value over the visited bins:
+//   ln Z = m + ln sum exp(a - m),  <E>, <E^2> the weighted means,
+//   C = beta^2 sum w (E - <E>)^2 / sum w  (taken about the mean).
+// One block per (group, beta); reductions in a fixed order.
+namespace {
+template <typename Op>
+__device__ __forceinline__ double block_reduce(double v, double* red, Op op) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = op(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_reweight(const GroupDesc* __restrict__ groups,
+                                                  const double* __restrict__ lnW,
+                                                  const int32_t* __restrict__ H,
+                                                  const double* __restrict__ beta, int nbeta,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  const int gi = blockIdx.x / nbeta, k = blockIdx.x - gi * nbeta;
+  const GroupDesc g = groups[gi];
+  const double b = beta[k];
+  const int32_t* h = H + g.bin_off;
+  const double* lw = lnW + g.bin_off;
+  auto expo = [&](int i) { return log((double)h[i]) - lw[i] - b * (double)(g.e_lo + i); };
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
+    if (h[i] > 0) m = fmax(m, expo(i));
+  m = block_reduce(m, red, [](double x, double y) { return fmax(x, y); });
+  double* o = out + 4 * ((size_t)gi * (size_t)nbeta + (size_t)k);
+  if (m == -INFINITY) {  // no visited bin (uniform over the block)
+    if (threadIdx.x < 4) o[threadIdx.x] = NAN;
+    return;
+  }
+  const auto add = [](double x, double y) { return x + y; };
+  double z = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
+    if (h[i] > 0) {
+      const double w = exp(expo(i) - m);
+      z += w;
+      s1 += w * (double)(g.e_lo + i);
+    }
+  z = block_reduce(z, red, add);
+  s1 = block_reduce(s1, red, add);
+  const double mean = s1 / z;
+  double s2 = 0.0, sc = 0.0;
+  for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
+    if (h[i] > 0) {
+      const double w = exp(expo(i) - m);
+      const double e = (double)(g.e_lo + i);
+      s2 += w * e * e;
+      sc += w * (e - mean) * (e - mean);
+    }
+  s2 = block_reduce(s2, red, add);
+  sc = block_reduce(sc, red, add);
+  if (threadIdx.x == 0) {
+    o[0] = m + log(z);
+    o[1] = mean;
+    o[2] = s2 / z;
+    o[3] = b * b * sc / z;
+  }
+}
+
 __global__ void k_bump(int32_t* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter += 1;
 }

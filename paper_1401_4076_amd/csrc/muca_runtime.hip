@@ -813,6 +813,22 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
   return (stop != MUCA_STOP_NONE && remaining > 0) ? MUCA_NOT_CONVERGED : MUCA_OK;
 }
 
+int mucaReweight(muca_ctx c, const double* lnW, const int32_t* H, const double* beta, int nbeta,
+                 double* out, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW || !H || !beta || !out)
+    return fail(MUCA_EINVAL, "lnW, H, beta and out must not be NULL");
+  if (nbeta < 1) return fail(MUCA_EINVAL, "nbeta must be >= 1, got %d", nbeta);
+  if ((int64_t)nbeta * c->ngroups > 0x7FFFFFFFLL)
+    return fail(MUCA_EINVAL, "ngroups x nbeta exceeds the grid limit");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  hipLaunchKernelGGL(muca::k_reweight, dim3((unsigned)(c->ngroups * nbeta)), dim3(256), 0, s,
+                     c->d_groups, lnW, H, beta, nbeta, out);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
 int mucaSetTunnelTarget(muca_ctx c, int target) {
   if (int r = check_ctx(c)) return r;
   if (target < 1) return fail(MUCA_EINVAL, "tunnelling target must be >= 1, got %d", target);

@@ -73,6 +73,7 @@ SIGNATURES = {
                                       _P(ctypes.c_uint32), _P(_i32), _P(ctypes.c_uint64)]),
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
     "mucaSetTunnelTarget": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mucaReweight": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "mucaGetTunnel": (ctypes.c_int, [_vp, _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
     "mucaMlpParamCount": (ctypes.c_int, []),
     "mucaMlpCreate": (ctypes.c_int, [_P(_vp), ctypes.c_int]),
@@ -240,6 +241,16 @@ class Context:
                                   int(stop) if stop is not None else (1 if stop_on_flat else 0),
                                   1 if resume else 0, it, fl, _stream(stream)))
         return rc, list(it), list(fl)
+
+    def reweight(self, lnW, H, beta, out, stream=None):
+        """Canonical ln Z, <E>, <E^2>, C per group and beta into out (device
+        float64, ngroups x len(beta) x 4); beta is a device float64 tensor."""
+        nb = int(beta.numel())
+        _check(lib().mucaReweight(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
+                                  _dev(H, torch.int32, self.total_bins, "H"),
+                                  _dev(beta, torch.float64, nb, "beta"), nb,
+                                  _dev(out, torch.float64, self.ngroups * nb * 4, "out"),
+                                  _stream(stream)))
 
     def set_tunnel_target(self, target):
         _check(lib().mucaSetTunnelTarget(self._h, int(target)))

@@ -318,7 +318,7 @@ def test_run_until_flat_per_group(variant):
     assert rc == 0 and all(fl) and len(set(it)) >= 4
 
 
-TUNNEL_GROUPS = [(2, 4, 2, 6, -1, 0), (2, 4, 3, 5), (3, 3, 3, 4), (2, 6, 5, 4, -4, -1),
+TUNNEL_GROUPS = [(2, 4, 2, 6, -1, 0), (2, 4, 3, 5), (3, 3, 3, 4), (2, 6, 5, 4, -3, 0),
                  (3, 6, 12, 3, -10, 0)]
 
 
