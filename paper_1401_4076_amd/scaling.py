@@ -39,6 +39,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def speedups(results):
+    """S_p = p x (mean iterations at p = 1) / (mean iterations at p) per result,
+    or None for all when p = 1 was not run."""
+    base = next((r for r in results if r["p"] == 1), None)
+    if base is None:
+        return [None] * len(results)
+    return [r["p"] * base["iters_mean"] / r["iters_mean"] for r in results]
+
+
 def runs_for(d, L, N, p, runs, seed, total_sweeps, target, max_iters, chunk, rule,
              max_seconds=None):
     """The runs of one p, all in one context; returns a summary dict."""
@@ -112,10 +121,9 @@ def main():
         out["results"].append(res)
         log(f"p={p}: {res['converged']}/{args.runs} converged, mean iterations "
             f"{res['iters_mean']:.2f} +- {res['iters_sem']:.2f}, {res['gpu_seconds']:.1f} s")
-    base = next((r for r in out["results"] if r["p"] == 1), None)
-    if base is not None:
-        for r in out["results"]:
-            r["speedup"] = r["p"] * base["iters_mean"] / r["iters_mean"]
+    for r, sp in zip(out["results"], speedups(out["results"])):
+        if sp is not None:
+            r["speedup"] = sp
     print(json.dumps(out), flush=True)
 
 
