@@ -253,6 +253,17 @@ int mucaSetTunnelTarget(muca_ctx ctx, int target);
  * nbeta >= 1, else MUCA_EINVAL; asynchronous on stream. */
 int mucaReweight(muca_ctx ctx, const double* lnW, const int32_t* H, const double* beta,
                  int nbeta, double* out, void* stream);
+
+/* Largest droplet (Sec. 3 follows condensation through the largest cluster
+ * of particles): out[w] (device, nwalkers int32) = number of particles in
+ * the largest set connected through nearest-neighbour bonds (periodic) in
+ * walker w's current configuration.  Every group must have V <= 32768
+ * sites, else MUCA_EINVAL.  A measurement during a production run is a call
+ * between sweeps (mucaSweep with sweeps = the measurement interval); the
+ * walkers' energies for binning come from mucaReadWalker or the caller's
+ * bookkeeping.  Asynchronous on stream; -1 marks an internal bound reached
+ * (not expected: the union-find loops are bounded by N). */
+int mucaLargestCluster(muca_ctx ctx, int32_t* out, void* stream);
 int mucaGetTunnel(muca_ctx ctx, uint32_t* last_end, uint32_t* trips);
 
 /* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's

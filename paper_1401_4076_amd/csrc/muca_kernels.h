@@ -38,6 +38,8 @@ __global__ void k_control(const GroupDesc* groups, const int32_t* H, int32_t* ac
                           int32_t* remaining, const uint32_t* tun, int stop, int tunnel_target);
 __global__ void k_reweight(const GroupDesc* groups, const double* lnW, const int32_t* H,
                            const double* beta, int nbeta, double* out);
+__global__ void k_largest_cluster(const GroupDesc* groups, const int32_t* wgroup,
+                                  const uint32_t* pos, int32_t* out);
 __global__ void k_bump(int32_t* counter);
 __global__ void k_fill_i32(int32_t* p, int32_t v, int n);
 __global__ void k_fill_f64(double* p, double v, int n);

@@ -396,6 +396,94 @@ __global__ void __launch_bounds__(256) k_reweight(const GroupDesc* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------- droplets
+// Size of the largest cluster of nearest-neighbour-bonded particles of each
+// walker (Sec. 3 follows condensation through the largest droplet).  One
+// block per walker.  LDS: a site -> particle map (int16, V <= 32768; reused
+// for the cluster sizes once the bonds are linked) and a union-find forest
+// over the particles.  A link is one compare-and-swap that points a root at
+// a smaller root, so parent chains strictly decrease: every walk up a chain
+// ends within N steps and every union retries at most N times (a retry
+// means another link took the root; at most N - 1 links exist).  The loops
+// are bounded by those counts; a bound that is ever reached reports -1.
+namespace {
+__device__ __forceinline__ int root_of(const int32_t* parent, int x, int n) {
+  for (int k = 0; k <= n; ++k) {
+    const int px = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (px == x) return x;
+    x = px;
+  }
+  return -1;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_largest_cluster(const GroupDesc* __restrict__ groups,
+                                                         const int32_t* __restrict__ wgroup,
+                                                         const uint32_t* __restrict__ pos,
+                                                         int32_t* __restrict__ out) {
+  // LDS (dynamic only): [best, error flag] [map / sizes: max(2V, 4N) bytes] [parent: N]
+  extern __shared__ uint32_t smem[];
+  const int w = blockIdx.x;
+  const GroupDesc g = groups[wgroup[w]];
+  const int V = g.V, N = g.N, L = g.L;
+  const int a_words = (V * 2 > N * 4 ? V * 2 + 3 : N * 4) / 4;  // max(2V, 4N) bytes
+  int32_t* flags = reinterpret_cast<int32_t*>(smem);
+  int16_t* map = reinterpret_cast<int16_t*>(smem + 2);
+  int32_t* cnt = reinterpret_cast<int32_t*>(smem + 2);
+  int32_t* parent = reinterpret_cast<int32_t*>(smem + 2) + a_words;
+  const uint32_t* p = pos + g.pos_off + (int64_t)(w - g.first_walker) * N;
+  for (int i = threadIdx.x; i < V; i += blockDim.x) map[i] = -1;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) parent[i] = i;
+  if (threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[1] = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) map[p[i]] = (int16_t)i;
+  __syncthreads();
+  bool bad = false;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int s = (int)p[i];
+    const int x = s % L, y = (s / L) % L, z = s / g.LL;
+    for (int dir = 0; dir < 2 * g.d; ++dir) {
+      const int axis = dir >> 1;
+      const int c = axis == 0 ? x : (axis == 1 ? y : z);
+      const int stride = axis == 0 ? 1 : (axis == 1 ? L : g.LL);
+      const int t = (dir & 1) == 0 ? (c == L - 1 ? s - (L - 1) * stride : s + stride)
+                                   : (c == 0 ? s + (L - 1) * stride : s - stride);
+      const int j = map[t];
+      if (j < 0 || j >= i) continue;  // each bond once, from its higher particle
+      int tries = 0;
+      for (; tries <= N; ++tries) {
+        const int a = root_of(parent, i, N), b = root_of(parent, j, N);
+        if (a < 0 || b < 0) {
+          tries = N + 1;
+          break;
+        }
+        if (a == b) break;
+        const int hi = a > b ? a : b, lo = a > b ? b : a;
+        if (atomicCAS(&parent[hi], hi, lo) == hi) break;
+      }
+      if (tries > N) bad = true;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;  // the map is done
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int r = root_of(parent, i, N);
+    if (r < 0) bad = true;
+    else atomicAdd(&cnt[r], 1);
+  }
+  __syncthreads();
+  int m = 0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) m = cnt[i] > m ? cnt[i] : m;
+  atomicMax(&flags[0], m);
+  if (bad) atomicOr(&flags[1], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) out[w] = flags[1] ? -1 : flags[0];
+}
+
 __global__ void k_bump(int32_t* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter += 1;
 }

@@ -829,6 +829,32 @@ int mucaReweight(muca_ctx c, const double* lnW, const int32_t* H, const double* 
   return MUCA_OK;
 }
 
+int mucaLargestCluster(muca_ctx c, int32_t* out, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!out) return fail(MUCA_EINVAL, "out must not be NULL");
+  size_t need = 8;  // LDS of k_largest_cluster: two flags, max(2V, 4N) bytes (word-rounded), 4N
+  for (int i = 0; i < c->ngroups; ++i) {
+    const GroupDesc& g = c->g[i];
+    if (g.V > 32768)
+      return fail(MUCA_EINVAL, "group %d: %d sites exceed the droplet measurement's 32768", i,
+                  g.V);
+    const size_t a = 2 * (size_t)g.V > 4 * (size_t)g.N ? (2 * (size_t)g.V + 3) / 4 * 4
+                                                          : 4 * (size_t)g.N;
+    need = std::max(need, a + 4 * (size_t)g.N);
+  }
+  if (need > c->lds_device)
+    return fail(MUCA_EINVAL, "droplet measurement needs %zu bytes of LDS per block", need);
+  // the kernel has no static LDS; allow exactly what this context needs
+  HIP_TRY(hipFuncSetAttribute((const void*)muca::k_largest_cluster,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  hipLaunchKernelGGL(muca::k_largest_cluster, dim3((unsigned)c->nwalkers), dim3(256), need, s,
+                     c->d_groups, c->d_wgroup, c->d_pos, out);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
 int mucaSetTunnelTarget(muca_ctx c, int target) {
   if (int r = check_ctx(c)) return r;
   if (target < 1) return fail(MUCA_EINVAL, "tunnelling target must be >= 1, got %d", target);

@@ -74,6 +74,7 @@ SIGNATURES = {
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
     "mucaSetTunnelTarget": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaReweight": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
+    "mucaLargestCluster": (ctypes.c_int, [_vp, _vp, _vp]),
     "mucaGetTunnel": (ctypes.c_int, [_vp, _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
     "mucaMlpParamCount": (ctypes.c_int, []),
     "mucaMlpCreate": (ctypes.c_int, [_P(_vp), ctypes.c_int]),
@@ -251,6 +252,12 @@ class Context:
                                   _dev(beta, torch.float64, nb, "beta"), nb,
                                   _dev(out, torch.float64, self.ngroups * nb * 4, "out"),
                                   _stream(stream)))
+
+    def largest_cluster(self, out, stream=None):
+        """Largest nearest-neighbour droplet of every walker into out (device
+        int32, nwalkers)."""
+        _check(lib().mucaLargestCluster(self._h, _dev(out, torch.int32, self.nwalkers, "out"),
+                                        _stream(stream)))
 
     def set_tunnel_target(self, target):
         _check(lib().mucaSetTunnelTarget(self._h, int(target)))
