@@ -45,3 +45,27 @@ def reweight(lnW, H, e_lo, betas):
         out[k, 2] = (w * Es * Es).sum() / z
         out[k, 3] = beta * beta * (w * (Es - mean) ** 2).sum() / z
     return out
+
+
+def reweight_observable(lnW, H, Osum, e_lo, betas):
+    """Canonical average of an observable O measured during a run with weights
+    W: Osum[b] is the sum of O over the H[b] measurements taken at
+    E = e_lo + b, so the microcanonical mean is Osum/H on visited bins and
+    <O>_beta = sum_E (Osum/H)(E) Omega(E) exp(-beta E) / Z, with the same
+    ln Omega and shift as reweight().  Returns an array of len(betas) (NaN
+    when no bin is visited)."""
+    lnW = np.asarray(lnW, dtype=np.float64)
+    H = np.asarray(H, dtype=np.int64)
+    Osum = np.asarray(Osum, dtype=np.float64)
+    E = e_lo + np.arange(len(H), dtype=np.float64)
+    seen = H > 0
+    out = np.full(len(betas), np.nan)
+    if not seen.any():
+        return out
+    ln_omega = np.log(H[seen].astype(np.float64)) - lnW[seen]
+    mean_o = Osum[seen] / H[seen]
+    for k, beta in enumerate(betas):
+        a = ln_omega - beta * E[seen]
+        w = np.exp(a - a.max())
+        out[k] = (w * mean_o).sum() / w.sum()
+    return out

@@ -21,7 +21,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from oracle.reweight_ref import reweight
+from oracle.droplet_ref import largest_cluster
+from oracle.reweight_ref import reweight, reweight_observable
 
 
 def _config_energies(d, L, N):
@@ -100,3 +101,33 @@ def test_reweighted_iteration_matches_exact():
     out = reweight(lnW, H, e_lo, [0.5])
     exact = _direct(Es, 0.5)[1]
     assert abs(out[0, 1] - exact) < 0.02 * abs(e_lo), (out[0, 1], exact)
+
+
+def test_observable_reweighting_against_direct_sums():
+    """<largest droplet>_beta over every configuration of 2D L = 4, N = 5
+    (direct canonical sums) equals the reweighting of a flat histogram whose
+    per-bin observable sums hold the exact microcanonical means."""
+    d, L, N = 2, 4, 5
+    V = L ** d
+    Ls = []
+    for c in itertools.combinations(range(V), N):
+        occ = np.zeros(V, dtype=np.uint8)
+        occ[list(c)] = 1
+        Ls.append(largest_cluster(occ, d, L))
+    Es = _config_energies(d, L, N)
+    Ls = np.array(Ls, dtype=np.float64)
+    e_lo = int(Es.min())
+    bins = np.arange(e_lo, 1)
+    counts = np.array([(Es == e).sum() for e in bins], dtype=np.float64)
+    micro = np.array([Ls[Es == e].mean() if (Es == e).any() else 0.0 for e in bins])
+    H = np.where(counts > 0, 500, 0)
+    lnW = np.where(counts > 0, -np.log(np.maximum(counts, 1)), 0.0)
+    Osum = micro * H
+    betas = [0.0, 0.7, 1.5, 3.0]
+    got = reweight_observable(lnW, H, Osum, e_lo, betas)
+    for k, beta in enumerate(betas):
+        w = np.exp(-beta * (Es - Es.min()))
+        assert got[k] == pytest.approx((w * Ls).sum() / w.sum(), rel=1e-12)
+    # O = E reproduces <E> of reweight()
+    np.testing.assert_allclose(reweight_observable(lnW, H, bins * H, e_lo, betas),
+                               reweight(lnW, H, e_lo, betas)[:, 1], rtol=1e-13)
