@@ -3,14 +3,19 @@
 One step = one iteration of the parallel multicanonical method (paper
 Sec. 2) over the whole batch of walkers: acceptance thresholds from lnW,
 `sweeps` sweeps of every walker (histogram fill and sum, eq. (2)), flatness
-test and the binary64 weight recursion.  The default workload is the batched
-2D lattice gas: 6 groups (L, rho) in {32, 48, 64} x {0.05, 0.10}, 4096
-walkers, 1e4 sweeps per iteration, starting from flat weights; inputs are
-synthetic and resident in device memory when timing starts.
+test and the binary64 weight recursion.  The default workload is the large
+3D lattice gas: L = 48, rho = 0.03 (N = 3318), 16384 walkers, starting from
+flat weights, 16 sweeps per walker per iteration (the rate does not depend on
+the sweep count: the per-iteration work outside the sweep takes well under a
+millisecond); inputs are synthetic and resident in device memory when timing
+starts.
 
 Prints one JSON line: move attempts/s (attempts = sum over walkers of
-sweeps x L^d, accepted or not), the VALU roofline of the sweep kernel and
-the CPU oracle's rate on a bounded sample of the same workload.
+sweeps x L^d, accepted or not), the roofline of the sweep kernel (device
+memory when the walker state lives there, else the VALU), with the VALU, HBM
+and LDS fractions from per-attempt algorithmic counts, and the CPU oracle's
+rate on a bounded sample of the same workload, on one core and on all the
+host cores the process may use.
 """
 import argparse
 import json
@@ -25,32 +30,55 @@ import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops/s
+# MI355X peaks: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU
+# lane-ops/s; HBM3E 8 TB/s; LDS 128 bytes per clock per CU.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
-# One Philox4x32-10 block: 10 rounds of two 32x32->64 products (quarter rate,
-# 4 full-rate equivalents each) and two three-input XORs.
-PHILOX_OPS = 10 * (2 * 4 + 2)
+HBM_PEAK = 8.0e12
+LDS_PEAK = 256 * 128 * 2.4e9
+
+# One Philox4x32-10 block: 10 rounds of two 32x32->64 products (quarter rate:
+# 4 full-rate lane-op equivalents each), two three-input XORs and the key
+# schedule.
+PHILOX_OPS = 10 * (2 * 4 + 2 + 1)
+
+BENCH_SWEEPS = {"large_3d": 16, "batched_3d": 16}
 
 
 def attempts_per_sweep(groups):
     return sum(g[3] * g[1] ** g[0] for g in groups)
 
 
-def philox_blocks_per_attempt(groups):
-    """Expected Philox blocks per attempt (weighted over walkers): block 0
-    always; block 1 when the first two candidate sites are occupied (~rho^2)."""
-    tot = sum(g[3] * g[1] ** g[0] for g in groups)
-    acc = 0.0
-    for d, L, N, w, *_ in groups:
-        rho = N / L ** d
-        acc += w * L ** d * (1.0 + rho * rho / (1.0 - rho))
-    return acc / tot
+def _weighted(groups, f):
+    """Walker-and-site weighted mean of f(d, rho) over the groups."""
+    tot = attempts_per_sweep(groups)
+    return sum(g[3] * g[1] ** g[0] * f(g[0], g[2] / g[1] ** g[0]) for g in groups) / tot
 
 
-def measured_traffic(workload, kernel_layout):
+def valu_ops_per_attempt(d, rho):
+    """Algorithmic full-rate 32-bit lane-ops of one attempt: Philox blocks
+    (block 0 always, further blocks when both candidate sites are occupied,
+    a geometric number with mean rho^2/(1 - rho)), three multiply-shift draws
+    (quarter-rate products), 3 ops per neighbour index of s_o and s_n (edge
+    compare, select, add: 4d sites), 2 per bit test (word index, bit extract:
+    4d sites), 6 per site-to-coordinate division for two sites (d - 1 each),
+    and 8 for the energy change, window check and threshold compare."""
+    return (PHILOX_OPS * (1.0 + rho * rho / (1.0 - rho)) + 3 * 4 + 3 * 4 * d + 2 * 4 * d +
+            6 * (d - 1) * 2 + 8)
+
+
+def state_bytes_per_attempt(d, rho):
+    """Algorithmic bytes of walker state an attempt reads: the particle's site
+    pos[k] (4), the occupation words of the candidate sites until an empty one
+    (4 / (1 - rho)), one word per neighbour of s_o and of s_n (2 x 2d x 4) and
+    the threshold entry (4).  Writes of accepted moves (two words and pos[k])
+    are not counted: a lower bound."""
+    return 4 + 4.0 / (1.0 - rho) + 2 * 2 * d * 4 + 4
+
+
+def measured_traffic(workload, kernel_layout, attempts):
     """HBM bytes per sweep launch from the committed rocprofv3 counter runs
-    (profiles/sweep_traffic.json), or None when the kernel source has changed
-    since the counters were taken or another kernel ran."""
+    (profiles/sweep_traffic.json: bytes per attempt), or None when the kernel
+    source has changed since the counters were taken or another kernel ran."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if not os.path.exists(path):
@@ -63,11 +91,9 @@ def measured_traffic(workload, kernel_layout):
                    for n in ("muca_sweep_sub.hip", "muca_device.h"))
     if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
         return None
-    want = {2: "k_sweep_sub<16", 3: "k_sweep_sub<64", 5: "k_sweep_sub<16",
-            6: "k_sweep_sub<16"}.get(kernel_layout)
-    if want is None or want not in rec["kernel"]:
+    if rec.get("layout") != kernel_layout:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec["bytes_per_attempt"] * attempts
 
 
 def cpu_threads():
@@ -101,6 +127,33 @@ def split_walkers(groups, parts):
     return out
 
 
+def first_walkers(groups, n):
+    """The groups restricted to global walker ids [0, n)."""
+    out, left = [], n
+    for g in groups:
+        if left <= 0:
+            break
+        k = min(left, g[3])
+        out.append(tuple(g[:3]) + (k,) + tuple(g[4:]))
+        left -= k
+    return out
+
+
+def sample_walkers(groups, target_attempts):
+    """Walkers (a prefix of the global ids, at least one) whose single sweep
+    makes about target_attempts attempts."""
+    total = sum(g[3] for g in groups)
+    n = 0
+    acc = 0
+    for g in groups:
+        for _ in range(g[3]):
+            if n > 0 and acc >= target_attempts:
+                return n
+            acc += g[1] ** g[0]
+            n += 1
+    return total
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -111,26 +164,43 @@ def cpu_model():
     return "unknown CPU"
 
 
-def cpu_baseline(groups, seed, sample_sweeps, threads):
-    """The oracle on the host, one instance per thread over disjoint ranges of
-    global walker ids (the paper's one-process-per-core scheme).  The oracle
-    is C called through ctypes, which releases the GIL, so the instances run
-    in parallel."""
+def cpu_baseline(groups, seed, threads, per_thread_attempts=6.0e7):
+    """The oracle on the host: one sweep of a prefix of the walkers on one
+    core, then one sweep of a larger prefix split over `threads` threads, one
+    oracle instance per thread over disjoint ranges of global walker ids (the
+    paper's one-process-per-core scheme).  The oracle is C called through
+    ctypes, which releases the GIL, so the instances run in parallel."""
     import oracle as O
     from concurrent.futures import ThreadPoolExecutor
-    total = sum(g[3] for g in groups)
-    refs = [O.RefContext(sub, seed, first_id=a) for sub, a in split_walkers(groups, threads)]
-    lnWs = [np.zeros(r.total_bins) for r in refs]
+
+    n1 = sample_walkers(groups, per_thread_attempts)
+    one = first_walkers(groups, n1)
+    r = O.RefContext(one, seed)
+    t0 = time.perf_counter()
+    H = r.sweep(np.zeros(r.total_bins), 1)
+    dt1 = time.perf_counter() - t0
+    assert int(H.sum()) == n1
+    a1 = attempts_per_sweep(one)
+    r.close()
+
+    nall = sample_walkers(groups, per_thread_attempts * threads)
+    allg = first_walkers(groups, nall)
+    refs = [O.RefContext(sub, seed, first_id=a) for sub, a in split_walkers(allg, threads)]
+    lnWs = [np.zeros(x.total_bins) for x in refs]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(len(refs)) as ex:
-        Hs = list(ex.map(lambda i: refs[i].sweep(lnWs[i], sample_sweeps), range(len(refs))))
+        Hs = list(ex.map(lambda i: refs[i].sweep(lnWs[i], 1), range(len(refs))))
     dt = time.perf_counter() - t0
-    n = attempts_per_sweep(groups) * sample_sweeps
-    assert sum(int(H.sum()) for H in Hs) == total * sample_sweeps
-    return {"value": n / dt, "unit": "attempts/s", "cores": len(refs), "kind": "oracle",
-            "sample": f"all {total} walkers x {sample_sweeps} sweeps ({n:.3g} attempts, flat "
-                      f"weights) in {dt:.1f} s on {len(refs)} threads ({cpu_model()}), one "
-                      f"oracle instance per thread over disjoint walker ranges"}
+    assert sum(int(h.sum()) for h in Hs) == nall
+    a = attempts_per_sweep(allg)
+    for x in refs:
+        x.close()
+    return {"value": a / dt, "unit": "attempts/s", "cores": len(refs), "kind": "oracle",
+            "single_core_value": a1 / dt1,
+            "sample": f"one sweep of walkers 0..{nall - 1} ({a:.3g} attempts, flat weights) "
+                      f"in {dt:.1f} s on {len(refs)} threads, one oracle instance per thread "
+                      f"over disjoint walker ranges; single core: one sweep of walkers "
+                      f"0..{n1 - 1} ({a1:.3g} attempts) in {dt1:.1f} s ({cpu_model()})"}
 
 
 def calibrate_copy(nbytes):
@@ -149,17 +219,15 @@ def calibrate_copy(nbytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched_2d", choices=sorted(W.WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large_3d", choices=sorted(W.WORKLOADS))
     ap.add_argument("--sweeps", type=int, default=None, help="sweeps per iteration")
     ap.add_argument("--layout", type=int, default=0,
                     help="0: autotune, else a MUCA_LAYOUT_* index (1 lane, 2 16 lanes/walker, "
                          "3 64 lanes/walker, 4 lookahead, 5/6 16 lanes with 2/1 walkers "
                          "per wavefront)")
-    ap.add_argument("--probe-sweeps", type=int, default=20, help="autotune probe length")
-    ap.add_argument("--cpu-sweeps", type=int, default=None,
-                    help="sweeps of the CPU oracle sample (default: ~4e8 attempts)")
+    ap.add_argument("--probe-sweeps", type=int, default=1, help="autotune probe length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
@@ -177,7 +245,7 @@ def main():
 
     wl = W.WORKLOADS[args.workload]
     groups, seed = wl["groups"], wl["seed"]
-    sweeps = args.sweeps or wl["sweeps"]
+    sweeps = args.sweeps or BENCH_SWEEPS.get(args.workload, wl["sweeps"])
     print(f"bench: workload={args.workload} groups={groups} sweeps={sweeps} "
           f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     ctx = M.Context(groups, seed)
@@ -191,6 +259,7 @@ def main():
               file=sys.stderr, flush=True)
     else:
         ctx.set_layout(args.layout)
+    state_lds, table_lds = ctx.placement()
     P = torch.zeros_like(lnW)
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
     flags = torch.zeros(ctx.ngroups, dtype=torch.int32, device=dev)
@@ -227,8 +296,28 @@ def main():
     dt = t1 - t0
     value = per_step * args.steps / dt
     sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ops = per_step * philox_blocks_per_attempt(groups) * PHILOX_OPS
-    achieved = ops / (sweep_ms * 1e-3)
+    kernel_rate = per_step / (sweep_ms * 1e-3)  # attempts/s inside the sweep launch
+    ops = _weighted(groups, valu_ops_per_attempt)
+    sbytes = _weighted(groups, state_bytes_per_attempt)
+    valu = {"achieved": ops * kernel_rate, "peak": VALU_PEAK_OPS, "unit": "int32 lane-op/s",
+            "frac": ops * kernel_rate / VALU_PEAK_OPS, "per_attempt": ops}
+    # the walker state is read from device memory or from LDS, not both
+    state_rate = sbytes * kernel_rate
+    hbm = {"achieved": 0.0 if state_lds else state_rate, "peak": HBM_PEAK, "unit": "B/s",
+           "per_attempt": 0.0 if state_lds else sbytes}
+    hbm["frac"] = hbm["achieved"] / HBM_PEAK
+    lds = {"achieved": state_rate if state_lds else 0.0, "peak": LDS_PEAK, "unit": "B/s",
+           "per_attempt": sbytes if state_lds else 0.0}
+    lds["frac"] = lds["achieved"] / LDS_PEAK
+    traffic = measured_traffic(args.workload, ctx.layout(), per_step)
+    if state_lds:
+        roof = {"bound": "alu", "achieved": valu["achieved"], "peak": VALU_PEAK_OPS,
+                "unit": "int32 lane-op/s", "frac": valu["frac"], "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm["achieved"] / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": hbm["frac"], "traffic": traffic}
+    roof.update({"valu": valu, "hbm": hbm, "lds": lds,
+                 "traffic_per_attempt": None if traffic is None else traffic / per_step})
     out = {
         "metric": "move attempts/s on 1 GPU",
         "value": value,
@@ -245,20 +334,15 @@ def main():
         "config": {"workload": args.workload, "groups": [list(g) for g in groups],
                    "walkers": sum(g[3] for g in groups), "sweeps_per_iter": sweeps,
                    "attempts_per_step": per_step, "rule": "berg", "layout": ctx.layout(),
+                   "state_in_lds": state_lds, "table_in_lds": table_lds,
                    "autotune_probe_ms": tune_ms},
         "sweep_kernel_ms": sweep_ms,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS,
-                     "unit": "int32 lane-op/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": measured_traffic(args.workload, ctx.layout())},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        cs = args.cpu_sweeps
-        if cs is None:  # ~4e8 attempts: ~15-20 s of single-core oracle work
-            cs = max(1, int(round(4e8 / attempts_per_sweep(groups))))
         nt = cpu_threads()
-        print(f"bench: CPU oracle sample, {cs} sweeps of all walkers on {nt} threads",
-              file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(groups, seed, cs, nt)
+        print(f"bench: CPU oracle sample on 1 and {nt} threads", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(groups, seed, nt)
     print(json.dumps(out), flush=True)
 
 

@@ -130,6 +130,12 @@ int mucaGetWindow(muca_ctx ctx, int group, int32_t* e_lo, int32_t* e_hi, int32_t
 int mucaSetLayout(muca_ctx ctx, int layout);
 int mucaGetLayout(muca_ctx ctx, int* layout);
 
+/* Where the resolved layout's sweep keeps the walker state and the threshold
+ * table: 1 = LDS for the whole launch, 0 = device memory (the one-walker-
+ * per-lane layout keeps both in device memory).  Host-side; no device work.
+ * Either output may be NULL. */
+int mucaGetPlacement(muca_ctx ctx, int* state_in_lds, int* table_in_lds);
+
 /* Largest LDS allocation (bytes per block of 256 lanes) the cooperative
  * layouts may use, capped by the device limit.  Walker state (occupation
  * bits and particle sites of the block's walkers) goes to LDS when it fits,
@@ -141,8 +147,19 @@ int mucaGetLayout(muca_ctx ctx, int* layout);
  * layout (LOOK4 then runs as SUB64); results are unchanged. */
 int mucaSetLdsLimit(muca_ctx ctx, int64_t bytes);
 
+/* Largest walker state (bytes of occupation bits and particle sites) that a
+ * cooperative launch keeps in flight at once when the state lives in device
+ * memory: the walker sets then run in rounds of whole blocks per compute
+ * unit, at least one block per compute unit.  The random accesses of the
+ * sweep are cheapest while the state in flight fits the device's last-level
+ * cache (256 MB on MI355X).  Default 224 MiB; 0 = no cap.  Results are
+ * unchanged; only the speed differs. */
+int mucaSetResidentLimit(muca_ctx ctx, int64_t bytes);
+
 /* Time every layout on `probe_sweeps` sweeps with weights lnW (device) and
- * keep the fastest; synchronous.  Walker state is saved before and restored
+ * keep the fastest; a cooperative layout whose walker state lives in device
+ * memory is timed with the context's resident limit (mucaSetResidentLimit)
+ * and without a limit, and the faster of the two is kept; synchronous.  Walker state is saved before and restored
  * after the probes, so the call does not change any later result.  chosen
  * (host, may be NULL) receives the layout, ms (host, may be NULL,
  * MUCA_NUM_LAYOUTS doubles) the probe time per layout index (0 where not
@@ -236,6 +253,7 @@ int mucaRun(muca_ctx ctx, double* lnW, double* P, int32_t* H, int sweeps_per_ite
  *   NULL; waits for the device) the end visited last (0 none yet, 1 e_lo,
  *   2 e_hi) and the trips completed. */
 int mucaSetTunnelTarget(muca_ctx ctx, int target);
+int mucaGetTunnel(muca_ctx ctx, uint32_t* last_end, uint32_t* trips);
 
 /* Canonical reweighting (Sec. 3: the multicanonical data are reweighted to
  * the temperatures of interest).  H is a histogram taken with weights lnW
@@ -257,14 +275,46 @@ int mucaReweight(muca_ctx ctx, const double* lnW, const int32_t* H, const double
 /* Largest droplet (Sec. 3 follows condensation through the largest cluster
  * of particles): out[w] (device, nwalkers int32) = number of particles in
  * the largest set connected through nearest-neighbour bonds (periodic) in
- * walker w's current configuration.  Every group must have V <= 32768
- * sites, else MUCA_EINVAL.  A measurement during a production run is a call
- * between sweeps (mucaSweep with sweeps = the measurement interval); the
- * walkers' energies for binning come from mucaReadWalker or the caller's
- * bookkeeping.  Asynchronous on stream; -1 marks an internal bound reached
- * (not expected: the union-find loops are bounded by N). */
+ * walker w's current configuration.  Any lattice size; the walker's sorted
+ * particle sites and a union-find forest sit in LDS, so a group may hold at
+ * most as many particles as fit (8 + 4 P + 4 N bytes per block, P the power
+ * of two >= N; N <= 16384 on MI355X), else MUCA_EINVAL.  Asynchronous on
+ * stream; -1 marks an internal bound reached (not expected: the union-find
+ * loops are bounded by N). */
 int mucaLargestCluster(muca_ctx ctx, int32_t* out, void* stream);
-int mucaGetTunnel(muca_ctx ctx, uint32_t* last_end, uint32_t* trips);
+
+/* The energy-binned droplet measurement of a production run: for every
+ * walker, its largest droplet (as mucaLargestCluster) is added to osum at
+ * the bin of the walker's current energy and ocount counts the measurement
+ * there (device arrays of total_bins int64 and int32, concatenated bin
+ * layout; accumulated, not cleared).  out (device, nwalkers int32) may be
+ * NULL, else it also receives the sizes.  Integer sums: exact and
+ * independent of the order of the walkers. */
+int mucaMeasureDroplets(muca_ctx ctx, long long* osum, int32_t* ocount, int32_t* out,
+                        void* stream);
+
+/* A production run with fixed weights lnW (Sec. 3: after the iteration the
+ * system is simulated with the converged weights and the measurements are
+ * reweighted): `measurements` rounds of (sweeps_between sweeps of every
+ * walker, then mucaMeasureDroplets).  H (device, total_bins int32) receives
+ * the histogram of all sweeps; osum and ocount are cleared first and receive
+ * the droplet sums and counts per bin at the measurement sweeps.  Same
+ * walker-state carry-over and overflow checks as mucaSweep (over the total
+ * sweeps).  Asynchronous on stream. */
+int mucaProduction(muca_ctx ctx, const double* lnW, int sweeps_between, int measurements,
+                   int32_t* H, long long* osum, int32_t* ocount, void* stream);
+
+/* Canonical average of an observable measured during a production run
+ * (Sec. 3): osum[b] is its sum over the ocount[b] measurements at bin b (as
+ * mucaProduction or mucaMeasureDroplets leave them), taken with weights lnW.
+ * out[g * nbeta + k] (device, ngroups x nbeta doubles) =
+ *   sum_E (osum / ocount)(E) Omega(E) exp(-beta_k E) / sum_E Omega(E) exp(-beta_k E),
+ * ln Omega(E) = ln ocount(E) - lnW(E) over the bins with ocount > 0 (NaN for
+ * a group without one).  Shifted by the largest exponent, binary64, fixed
+ * reduction order; asynchronous on stream. */
+int mucaReweightObservable(muca_ctx ctx, const double* lnW, const int32_t* ocount,
+                           const long long* osum, const double* beta, int nbeta, double* out,
+                           void* stream);
 
 /* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's
  * stream instead of replaying the captured graph (same results). */

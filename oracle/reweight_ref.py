@@ -1,9 +1,9 @@
 """Reference of the canonical reweighting after the weight iteration.
 
 TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Plain numpy in binary64, written
-from the definitions.  Sec. 3 states the motivation: the multicanonical run
-drives the system between the evaporated and the condensed phase and the
-results are reweighted to the relevant temperatures afterwards.
+from the definitions.  Why (Sec. 3): a multicanonical run samples both the
+gas-like and the droplet states in one simulation, and canonical averages at
+any temperature follow from its data afterwards.
 
 A run with weights W(E) visits energy E with probability proportional to
 Omega(E) W(E), so its histogram H(E) estimates the density of states up to

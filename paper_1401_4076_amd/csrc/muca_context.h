@@ -18,6 +18,9 @@ int fail(int code, const char* fmt, ...);
 }  // namespace muca_detail
 
 constexpr int64_t kLdsBytes = 160 * 1024;  // LDS per CU of gfx950
+// Default cap of the walker state in flight when it lives in device memory:
+// below the 256 MB last-level (Infinity) cache of MI355X.
+constexpr size_t kResidentBytes = size_t(224) << 20;
 
 struct muca_context {
   int device = 0;
@@ -76,7 +79,24 @@ struct muca_context {
     }
   } graph_key{};
   size_t lds_limit = kLdsBytes;  // LDS a cooperative block may use
+  // walker state (bytes) a device-memory-state launch keeps in flight
+  size_t resident_limit = kResidentBytes;
   size_t lds_device = 64 * 1024;  // device maximum per block
+
+  // Forget the cooperative task tables (rebuilt on the next launch) and the
+  // captured iteration, e.g. after a change of the LDS or resident limit.
+  void drop_tables() {
+    (void)hipDeviceSynchronize();
+    for (auto& q : coop) {
+      (void)hipFree(q.d_tasks);
+      (void)hipFree(q.d_first);
+      q = Coop{};
+    }
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
 
   ~muca_context() {
     (void)hipFree(d_groups);

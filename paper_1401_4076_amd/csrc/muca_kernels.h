@@ -39,9 +39,14 @@ __global__ void k_control(const GroupDesc* groups, const int32_t* H, int32_t* ac
 __global__ void k_reweight(const GroupDesc* groups, const double* lnW, const int32_t* H,
                            const double* beta, int nbeta, double* out);
 __global__ void k_largest_cluster(const GroupDesc* groups, const int32_t* wgroup,
-                                  const uint32_t* pos, int32_t* out);
+                                  const uint32_t* pos, const int32_t* E, int32_t* out,
+                                  long long* osum, int32_t* ocount);
+__global__ void k_reweight_obs(const GroupDesc* groups, const double* lnW, const int32_t* cnt,
+                               const long long* osum, const double* beta, int nbeta,
+                               double* out);
 __global__ void k_bump(int32_t* counter);
 __global__ void k_fill_i32(int32_t* p, int32_t v, int n);
 __global__ void k_fill_f64(double* p, double v, int n);
+__global__ void k_fill_i64(long long* p, long long v, int n);
 
 }  // namespace muca

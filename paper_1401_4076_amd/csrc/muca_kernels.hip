@@ -399,13 +399,19 @@ __global__ void __launch_bounds__(256) k_reweight(const GroupDesc* __restrict__ 
 // ---------------------------------------------------------------- droplets
 // Size of the largest cluster of nearest-neighbour-bonded particles of each
 // walker (Sec. 3 follows condensation through the largest droplet).  One
-// block per walker.  LDS: a site -> particle map (int16, V <= 32768; reused
-// for the cluster sizes once the bonds are linked) and a union-find forest
-// over the particles.  A link is one compare-and-swap that points a root at
-// a smaller root, so parent chains strictly decrease: every walk up a chain
-// ends within N steps and every union retries at most N times (a retry
-// means another link took the root; at most N - 1 links exist).  The loops
-// are bounded by those counts; a bound that is ever reached reports -1.
+// block per walker.  LDS: the walker's particle sites, sorted (bitonic), so
+// that a neighbour site is found among the occupied ones by binary search for
+// any lattice size; then a union-find forest over the positions of the sorted
+// array (the clusters do not depend on how particles are numbered).  A link
+// is one compare-and-swap that points a root at a smaller root, so parent
+// chains strictly decrease: every walk up a chain ends within N steps and
+// every union retries at most N times (a retry means another link took the
+// root; at most N - 1 links exist).  The loops are bounded by those counts; a
+// bound that is ever reached reports -1.
+//
+// With osum != nullptr the size is also added, at the walker's current
+// energy bin, to osum (int64, exact) and ocount counts the measurement: the
+// energy-binned measurement of a production run.
 namespace {
 __device__ __forceinline__ int root_of(const int32_t* parent, int x, int n) {
   for (int k = 0; k <= n; ++k) {
@@ -415,35 +421,61 @@ __device__ __forceinline__ int root_of(const int32_t* parent, int x, int n) {
   }
   return -1;
 }
+
+// Index of site t in the ascending array S[0, n), or -1.
+__device__ __forceinline__ int find_site(const uint32_t* S, int n, uint32_t t) {
+  int lo = 0, hi = n;  // first index with S[i] >= t lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (S[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && S[lo] == t) ? lo : -1;
+}
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_largest_cluster(const GroupDesc* __restrict__ groups,
-                                                         const int32_t* __restrict__ wgroup,
-                                                         const uint32_t* __restrict__ pos,
-                                                         int32_t* __restrict__ out) {
-  // LDS (dynamic only): [best, error flag] [map / sizes: max(2V, 4N) bytes] [parent: N]
+__global__ void __launch_bounds__(256) k_largest_cluster(
+    const GroupDesc* __restrict__ groups, const int32_t* __restrict__ wgroup,
+    const uint32_t* __restrict__ pos, const int32_t* __restrict__ E, int32_t* __restrict__ out,
+    long long* __restrict__ osum, int32_t* __restrict__ ocount) {
+  // LDS (dynamic only): [best, error flag] [S: npad sorted sites, later the
+  // cluster sizes] [parent: N]
   extern __shared__ uint32_t smem[];
   const int w = blockIdx.x;
   const GroupDesc g = groups[wgroup[w]];
-  const int V = g.V, N = g.N, L = g.L;
-  const int a_words = (V * 2 > N * 4 ? V * 2 + 3 : N * 4) / 4;  // max(2V, 4N) bytes
+  const int N = g.N, L = g.L;
+  int npad = 1;
+  while (npad < N) npad <<= 1;
   int32_t* flags = reinterpret_cast<int32_t*>(smem);
-  int16_t* map = reinterpret_cast<int16_t*>(smem + 2);
-  int32_t* cnt = reinterpret_cast<int32_t*>(smem + 2);
-  int32_t* parent = reinterpret_cast<int32_t*>(smem + 2) + a_words;
+  uint32_t* S = smem + 2;
+  int32_t* cnt = reinterpret_cast<int32_t*>(S);
+  int32_t* parent = reinterpret_cast<int32_t*>(S + npad);
   const uint32_t* p = pos + g.pos_off + (int64_t)(w - g.first_walker) * N;
-  for (int i = threadIdx.x; i < V; i += blockDim.x) map[i] = -1;
+  for (int i = threadIdx.x; i < npad; i += blockDim.x) S[i] = i < N ? p[i] : 0xFFFFFFFFu;
   for (int i = threadIdx.x; i < N; i += blockDim.x) parent[i] = i;
   if (threadIdx.x == 0) {
     flags[0] = 0;
     flags[1] = 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N; i += blockDim.x) map[p[i]] = (int16_t)i;
-  __syncthreads();
+  // bitonic sort, ascending (the padding sorts to the end)
+  for (int k = 2; k <= npad; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+        const int ij = i ^ j;
+        if (ij > i) {
+          const uint32_t a = S[i], b = S[ij];
+          if ((a > b) == ((i & k) == 0)) {
+            S[i] = b;
+            S[ij] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
   bool bad = false;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const int s = (int)p[i];
+    const int s = (int)S[i];
     const int x = s % L, y = (s / L) % L, z = s / g.LL;
     for (int dir = 0; dir < 2 * g.d; ++dir) {
       const int axis = dir >> 1;
@@ -451,8 +483,8 @@ __global__ void __launch_bounds__(256) k_largest_cluster(const GroupDesc* __rest
       const int stride = axis == 0 ? 1 : (axis == 1 ? L : g.LL);
       const int t = (dir & 1) == 0 ? (c == L - 1 ? s - (L - 1) * stride : s + stride)
                                    : (c == 0 ? s + (L - 1) * stride : s - stride);
-      const int j = map[t];
-      if (j < 0 || j >= i) continue;  // each bond once, from its higher particle
+      const int j = find_site(S, N, (uint32_t)t);
+      if (j < 0 || j >= i) continue;  // each bond once, from its higher index
       int tries = 0;
       for (; tries <= N; ++tries) {
         const int a = root_of(parent, i, N), b = root_of(parent, j, N);
@@ -468,7 +500,7 @@ __global__ void __launch_bounds__(256) k_largest_cluster(const GroupDesc* __rest
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;  // the map is done
+  for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;  // the sites are done
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const int r = root_of(parent, i, N);
@@ -481,7 +513,59 @@ __global__ void __launch_bounds__(256) k_largest_cluster(const GroupDesc* __rest
   atomicMax(&flags[0], m);
   if (bad) atomicOr(&flags[1], 1);
   __syncthreads();
-  if (threadIdx.x == 0) out[w] = flags[1] ? -1 : flags[0];
+  if (threadIdx.x == 0) {
+    const int size = flags[1] ? -1 : flags[0];
+    if (out) out[w] = size;
+    if (osum) {
+      const int b = E[w] - g.e_lo;  // the walker's energy lies in its window
+      atomicAdd(reinterpret_cast<unsigned long long*>(&osum[g.bin_off + b]),
+                (unsigned long long)(long long)size);
+      atomicAdd(&ocount[g.bin_off + b], 1);
+    }
+  }
+}
+
+// Canonical average of an observable measured during a production run
+// (Sec. 3: the data are reweighted to the temperatures of interest): osum[b]
+// is the sum of the observable over the cnt[b] measurements taken at bin b,
+// so (osum / cnt)(E) is its microcanonical mean, and
+//   <O>_beta = sum_E (osum / cnt)(E) Omega(E) exp(-beta E) / sum_E Omega(E) exp(-beta E)
+// with ln Omega(E) = ln cnt(E) - ln W(E) over the bins with cnt > 0.  One block
+// per (group, beta); the sums are shifted by the largest exponent and reduced
+// in a fixed order.  NaN for a group without a measurement.
+__global__ void __launch_bounds__(256) k_reweight_obs(const GroupDesc* __restrict__ groups,
+                                                      const double* __restrict__ lnW,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const long long* __restrict__ osum,
+                                                      const double* __restrict__ beta, int nbeta,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  const int gi = blockIdx.x / nbeta, k = blockIdx.x - gi * nbeta;
+  const GroupDesc g = groups[gi];
+  const double b = beta[k];
+  const int32_t* h = cnt + g.bin_off;
+  const long long* o = osum + g.bin_off;
+  const double* lw = lnW + g.bin_off;
+  auto expo = [&](int i) { return log((double)h[i]) - lw[i] - b * (double)(g.e_lo + i); };
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
+    if (h[i] > 0) m = fmax(m, expo(i));
+  m = block_reduce(m, red, [](double x, double y) { return fmax(x, y); });
+  if (m == -INFINITY) {  // no measurement (uniform over the block)
+    if (threadIdx.x == 0) out[(size_t)gi * nbeta + k] = NAN;
+    return;
+  }
+  const auto add = [](double x, double y) { return x + y; };
+  double z = 0.0, so = 0.0;
+  for (int i = threadIdx.x; i < g.nbins; i += blockDim.x)
+    if (h[i] > 0) {
+      const double w = exp(expo(i) - m);
+      z += w;
+      so += w * ((double)o[i] / (double)h[i]);
+    }
+  z = block_reduce(z, red, add);
+  so = block_reduce(so, red, add);
+  if (threadIdx.x == 0) out[(size_t)gi * nbeta + k] = so / z;
 }
 
 __global__ void k_bump(int32_t* counter) {
@@ -489,6 +573,10 @@ __global__ void k_bump(int32_t* counter) {
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_i64(long long* __restrict__ p, long long v, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 

@@ -117,14 +117,20 @@ int check_ctx(muca_ctx c) {
   return MUCA_OK;
 }
 
-int enqueue_thresholds(muca_ctx c, const double* lnW, hipStream_t s) {
+// Acceptance thresholds of every group into thr (the context's table, or
+// the static workspace of the allocation-free sweep).
+int enqueue_thresholds_to(muca_ctx c, const double* lnW, uint32_t* thr, hipStream_t s) {
   int maxe = 0;
   for (const auto& q : c->g) maxe = std::max(maxe, q.nbins * q.nd);
   dim3 grid((unsigned)std::min(1024, (maxe + 255) / 256), (unsigned)c->ngroups);
-  hipLaunchKernelGGL(muca::k_thresholds, grid, dim3(256), 0, s, c->d_groups, lnW, c->d_thr,
+  hipLaunchKernelGGL(muca::k_thresholds, grid, dim3(256), 0, s, c->d_groups, lnW, thr,
                      c->d_status);
   LAUNCH_CHECK();
   return MUCA_OK;
+}
+
+int enqueue_thresholds(muca_ctx c, const double* lnW, hipStream_t s) {
+  return enqueue_thresholds_to(c, lnW, c->d_thr, s);
 }
 
 int resolved_layout(muca_ctx c) {
@@ -143,22 +149,36 @@ constexpr int kCoopLanes[5] = {16, 64, 16, 16, 64};  // lanes per walker
 constexpr int kCoopSpread[5] = {1, 1, 2, 4, 1};      // 16-lane rows per walker row used
 constexpr bool kCoopPacked[5] = {true, true, true, true, false};
 
+// Host-side sizes of a cooperative layout: LDS bytes for the walker state of
+// the largest set (need), and the context's largest histogram and threshold
+// table of one group (hist_bytes, tbl_bytes).  No device work.
+size_t coop_sizes(muca_ctx c, int which) {
+  const int wpb = 256 / kCoopLanes[which] / kCoopSpread[which];
+  size_t need = 0;
+  c->hist_bytes = 0;
+  c->tbl_bytes = 0;
+  for (const auto& g : c->g) {
+    // per walker: (site, coordinates) pairs, bits rounded up to whole pairs;
+    // one word of alignment slack before the first slot
+    need = std::max(need, (size_t)wpb * (size_t)(2 * g.N + ((g.words + 1) & ~1)) *
+                              sizeof(uint32_t) + sizeof(uint32_t));
+    c->hist_bytes = std::max(c->hist_bytes, (size_t)g.nbins * sizeof(int32_t));
+    c->tbl_bytes = std::max(c->tbl_bytes, (size_t)g.nbins * (size_t)g.nd * sizeof(uint32_t));
+  }
+  return need;
+}
+
 int build_coop(muca_ctx c, int which) {
   auto& q = c->coop[which];
   if (q.d_tasks) return MUCA_OK;
   const int G = kCoopLanes[which];
   const int wpb = 256 / G / kCoopSpread[which];
   std::vector<std::vector<SweepTask>> per(c->ngroups);
-  size_t need = 0;
+  const size_t need = coop_sizes(c, which);
   for (int i = 0; i < c->ngroups; ++i) {
     const GroupDesc& g = c->g[i];
     for (int f = 0; f < g.walkers; f += wpb)
       per[i].push_back(SweepTask{i, g.first_walker + f, std::min(wpb, g.walkers - f), 0});
-    // per walker: (site, coordinates) pairs, bits rounded up to whole pairs;
-    // one word of alignment slack before the first slot
-    need = std::max(need, (size_t)wpb * (size_t)(2 * g.N + ((g.words + 1) & ~1)) *
-                              sizeof(uint32_t) + sizeof(uint32_t));
-    c->hist_bytes = std::max(c->hist_bytes, (size_t)g.nbins * sizeof(int32_t));
   }
   std::vector<SweepTask> sets;
   for (size_t r = 0;; ++r) {
@@ -173,11 +193,25 @@ int build_coop(muca_ctx c, int which) {
   const int n = (int)sets.size(), C = std::max(1, c->num_cu);
   std::vector<SweepTask> tasks;
   std::vector<int32_t> first;
-  if (!kCoopPacked[which] || n <= C) {
+  // With walker state in device memory, cap the state in flight at once
+  // (resident_limit bytes): a population whose state exceeds the device's
+  // last-level cache runs faster in rounds that fit it.
+  const size_t cap = std::min(c->lds_limit, c->lds_device);
+  const bool state_lds = !c->bricked && need + c->hist_bytes <= cap;
+  int Bmax = n;
+  if (!state_lds && c->resident_limit > 0) {
+    size_t set_bytes = 1;
+    for (const auto& t : sets)
+      set_bytes = std::max(set_bytes, (size_t)t.count *
+                                          ((size_t)c->g[t.group].words + c->g[t.group].N) *
+                                          sizeof(uint32_t));
+    Bmax = std::max(C, (int)(c->resident_limit / set_bytes / (size_t)C) * C);
+  }
+  if (!kCoopPacked[which] || (n <= C && n <= Bmax)) {
     tasks = sets;
     for (int b = 0; b <= n; ++b) first.push_back(b);
   } else {
-    const int B = (n / C) * C;
+    const int B = std::min((n / C) * C, Bmax);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -207,9 +241,6 @@ int build_coop(muca_ctx c, int which) {
   q.ntasks = (int)tasks.size();
   q.nblocks = (int)first.size() - 1;
   q.need = need;
-  c->tbl_bytes = 0;
-  for (const auto& g : c->g)
-    c->tbl_bytes = std::max(c->tbl_bytes, (size_t)g.nbins * (size_t)g.nd * sizeof(uint32_t));
   if (int r = dev_alloc(&q.d_tasks, tasks.size())) return r;
   if (int r = dev_alloc(&q.d_first, first.size())) return r;
   HIP_TRY(hipMemcpy(q.d_tasks, tasks.data(), sizeof(SweepTask) * tasks.size(),
@@ -219,11 +250,19 @@ int build_coop(muca_ctx c, int which) {
   return MUCA_OK;
 }
 
+// Where a cooperative launch finds its tables: block b runs tasks
+// [first[b], first[b + 1]); need = LDS bytes of the largest set's state.
+struct CoopTables {
+  const SweepTask* tasks;
+  const int32_t* first;
+  int nblocks;
+  size_t need;
+  const uint32_t* thr;
+};
+
 template <int G>
-int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* active,
-                hipStream_t s) {
-  if (int r = build_coop(c, which)) return r;
-  const auto& q = c->coop[which];
+int launch_coop_tables(muca_ctx c, int which, const CoopTables& q, int sweeps, int32_t* H,
+                       const int32_t* active, hipStream_t s) {
   const size_t cap = std::min(c->lds_limit, c->lds_device);
   // LDS-resident walker state comes with a block histogram in LDS
   const bool state_lds = !c->bricked && q.need + c->hist_bytes <= cap;
@@ -241,30 +280,51 @@ int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* ac
                                    : muca::k_sweep_sub<16, false, false, true>)
                         : (tbl_lds ? muca::k_sweep_sub<64, false, true, false>
                                    : muca::k_sweep_sub<64, false, false, false>);
-  hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
-                     q.d_first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, c->d_thr, H,
-                     active,
+  hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.tasks,
+                     q.first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, q.thr, H, active,
                      sweeps, c->first_id, c->seed32, tbl_words,
                      state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0, kCoopSpread[which]);
   LAUNCH_CHECK();
   return MUCA_OK;
 }
 
+template <int G>
+int launch_coop(muca_ctx c, int which, int sweeps, int32_t* H, const int32_t* active,
+                hipStream_t s) {
+  if (int r = build_coop(c, which)) return r;
+  const auto& q = c->coop[which];
+  return launch_coop_tables<G>(c, which, CoopTables{q.d_tasks, q.d_first, q.nblocks, q.need,
+                                                    c->d_thr},
+                               sweeps, H, active, s);
+}
+
 // Lookahead layout: blocks of four walkers (one per wavefront), walker state
-// and block histogram in LDS; falls back to SUB64 when they do not fit.
-int launch_look(muca_ctx c, int sweeps, int32_t* H, const int32_t* active, hipStream_t s) {
-  if (int r = build_coop(c, 4)) return r;
-  const auto& q = c->coop[4];
+// and block histogram in LDS; the caller falls back to SUB64 when they do not
+// fit (look_fits).  One task per block.
+bool look_fits(muca_ctx c, size_t need) {
   const size_t cap = std::min(c->lds_limit, c->lds_device);
-  if (c->bricked || q.need + c->hist_bytes > cap) return launch_coop<64>(c, 1, sweeps, H, active, s);
-  const size_t state = q.need + c->hist_bytes;
+  return !c->bricked && need + c->hist_bytes <= cap;
+}
+
+void launch_look_tables(muca_ctx c, const SweepTask* tasks, int ntasks, size_t need,
+                        const uint32_t* thr, int sweeps, int32_t* H, const int32_t* active,
+                        hipStream_t s) {
+  const size_t cap = std::min(c->lds_limit, c->lds_device);
+  const size_t state = need + c->hist_bytes;
   const bool tbl_lds = state + c->tbl_bytes <= cap;
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
   auto kern = tbl_lds ? muca::k_sweep_look<true> : muca::k_sweep_look<false>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)q.ntasks), dim3(256), dyn, s, c->d_groups, q.d_tasks,
-                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, c->d_thr, H, active, sweeps,
+  hipLaunchKernelGGL(kern, dim3((unsigned)ntasks), dim3(256), dyn, s, c->d_groups, tasks,
+                     c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, thr, H, active, sweeps,
                      c->first_id, c->seed32, tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0,
                      (int)(c->hist_bytes / sizeof(int32_t)));
+}
+
+int launch_look(muca_ctx c, int sweeps, int32_t* H, const int32_t* active, hipStream_t s) {
+  if (int r = build_coop(c, 4)) return r;
+  const auto& q = c->coop[4];
+  if (!look_fits(c, q.need)) return launch_coop<64>(c, 1, sweeps, H, active, s);
+  launch_look_tables(c, q.d_tasks, q.ntasks, q.need, c->d_thr, sweeps, H, active, s);
   LAUNCH_CHECK();
   return MUCA_OK;
 }
@@ -560,6 +620,8 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
   int rc = MUCA_OK;
   double best = 1e300;
   int pick = MUCA_LAYOUT_SUB16;
+  const size_t resident0 = c->resident_limit;
+  size_t pick_rl = resident0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   auto save = [&](bool back) -> int {
     const auto k = hipMemcpyDeviceToDevice;
@@ -588,19 +650,36 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     if ((r = save(false))) return r;
     if ((r = enqueue_thresholds(c, lnW, s))) return r;
     for (int lay = MUCA_LAYOUT_LANE; lay < MUCA_NUM_LAYOUTS; ++lay) {
-      if ((r = enqueue_zero_hist(c, h, c->d_ones, s))) return r;
-      HIP_TRY(hipEventRecord(ev0, s));
-      if ((r = enqueue_sweep_kernel(c, lay, probe_sweeps, h, c->d_ones, s))) return r;
-      HIP_TRY(hipEventRecord(ev1, s));
-      HIP_TRY(hipEventSynchronize(ev1));
-      float t = 0.f;
-      HIP_TRY(hipEventElapsedTime(&t, ev0, ev1));
-      if (ms) ms[lay] = t;
-      if (t < best) {
-        best = t;
-        pick = lay;
+      // cooperative layouts with walker state in device memory: with the
+      // resident cap and without it
+      const int which = lay == MUCA_LAYOUT_SUB16 ? 0 : lay == MUCA_LAYOUT_SUB64 ? 1
+                      : lay == MUCA_LAYOUT_LOOK4 ? 4 : lay == MUCA_LAYOUT_SUB16X2 ? 2
+                      : lay == MUCA_LAYOUT_SUB16X1 ? 3 : -1;
+      const size_t capb = std::min(c->lds_limit, c->lds_device);
+      const bool dev_state =
+          which >= 0 && (c->bricked || coop_sizes(c, which) + c->hist_bytes > capb);
+      const int nres = dev_state && resident0 > 0 ? 2 : 1;
+      for (int v = 0; v < nres; ++v) {
+        const size_t rl = v == 0 ? resident0 : 0;
+        if (rl != c->resident_limit) {
+          c->resident_limit = rl;
+          c->drop_tables();
+        }
+        if ((r = enqueue_zero_hist(c, h, c->d_ones, s))) return r;
+        HIP_TRY(hipEventRecord(ev0, s));
+        if ((r = enqueue_sweep_kernel(c, lay, probe_sweeps, h, c->d_ones, s))) return r;
+        HIP_TRY(hipEventRecord(ev1, s));
+        HIP_TRY(hipEventSynchronize(ev1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, ev0, ev1));
+        if (ms && (v == 0 || t < ms[lay])) ms[lay] = t;
+        if (t < best) {
+          best = t;
+          pick = lay;
+          pick_rl = rl;
+        }
+        if ((r = save(true))) return r;
       }
-      if ((r = save(true))) return r;
     }
     HIP_TRY(hipStreamSynchronize(s));
     return MUCA_OK;
@@ -616,9 +695,38 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
   (void)hipFree(h);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  if (c->resident_limit != pick_rl) {
+    c->resident_limit = pick_rl;
+    c->drop_tables();
+  }
   if (rc) return rc;
   c->tuned = pick;
   if (chosen) *chosen = pick;
+  return MUCA_OK;
+}
+
+int mucaGetPlacement(muca_ctx c, int* state_in_lds, int* table_in_lds) {
+  if (int r = check_ctx(c)) return r;
+  const int layout = resolved_layout(c);
+  int which = -1;
+  switch (layout) {
+    case MUCA_LAYOUT_SUB16: which = 0; break;
+    case MUCA_LAYOUT_SUB64: which = 1; break;
+    case MUCA_LAYOUT_LOOK4: which = 4; break;
+    case MUCA_LAYOUT_SUB16X2: which = 2; break;
+    case MUCA_LAYOUT_SUB16X1: which = 3; break;
+    default: break;
+  }
+  int st = 0, tb = 0;
+  if (which >= 0) {
+    const size_t need = coop_sizes(c, which);
+    const size_t cap = std::min(c->lds_limit, c->lds_device);
+    st = (!c->bricked && need + c->hist_bytes <= cap) ? 1 : 0;
+    const size_t state = st ? need + c->hist_bytes : 0;
+    tb = (c->lds_limit > 0 && state + c->tbl_bytes <= cap) ? 1 : 0;
+  }
+  if (state_in_lds) *state_in_lds = st;
+  if (table_in_lds) *table_in_lds = tb;
   return MUCA_OK;
 }
 
@@ -631,7 +739,20 @@ int mucaSetGraph(muca_ctx c, int enable) {
 int mucaSetLdsLimit(muca_ctx c, int64_t bytes) {
   if (int r = check_ctx(c)) return r;
   if (bytes < 0 || bytes > kLdsBytes) return fail(MUCA_EINVAL, "LDS limit must be in [0, 163840]");
-  c->lds_limit = (size_t)bytes;
+  if ((size_t)bytes != c->lds_limit) {
+    c->lds_limit = (size_t)bytes;
+    c->drop_tables();
+  }
+  return MUCA_OK;
+}
+
+int mucaSetResidentLimit(muca_ctx c, int64_t bytes) {
+  if (int r = check_ctx(c)) return r;
+  if (bytes < 0) return fail(MUCA_EINVAL, "resident limit must be >= 0");
+  if ((size_t)bytes != c->resident_limit) {
+    c->resident_limit = (size_t)bytes;
+    c->drop_tables();
+  }
   return MUCA_OK;
 }
 
@@ -829,28 +950,113 @@ int mucaReweight(muca_ctx c, const double* lnW, const int32_t* H, const double* 
   return MUCA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// LDS bytes of the droplet kernel for this context (two flags, the sorted
+// sites padded to a power of two, the union-find parents), or 0 with the
+// error set when a group does not fit.
+size_t droplet_lds(muca_ctx c) {
+  size_t need = 0;
+  for (int i = 0; i < c->ngroups; ++i) {
+    size_t npad = 1;
+    while (npad < (size_t)c->g[i].N) npad <<= 1;
+    need = std::max(need, 2 * sizeof(int32_t) + 4 * npad + 4 * (size_t)c->g[i].N);
+  }
+  if (need > c->lds_device) {
+    fail(MUCA_EINVAL, "droplet measurement needs %zu bytes of LDS per block (device: %zu)",
+         need, c->lds_device);
+    return 0;
+  }
+  return need;
+}
+
+int enqueue_droplets(muca_ctx c, int32_t* out, long long* osum, int32_t* ocount, size_t need,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(muca::k_largest_cluster, dim3((unsigned)c->nwalkers), dim3(256), need, s,
+                     c->d_groups, c->d_wgroup, c->d_pos, c->d_E, out, osum, ocount);
+  LAUNCH_CHECK();
+  return MUCA_OK;
+}
+
+// The droplet kernel's dynamic LDS limit, raised to what the context needs
+// (outside any stream capture: a host-side attribute).
+int droplet_attr(size_t need) {
+  HIP_TRY(hipFuncSetAttribute((const void*)muca::k_largest_cluster,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+  return MUCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mucaLargestCluster(muca_ctx c, int32_t* out, void* stream) {
   if (int r = check_ctx(c)) return r;
   if (!out) return fail(MUCA_EINVAL, "out must not be NULL");
-  size_t need = 8;  // LDS of k_largest_cluster: two flags, max(2V, 4N) bytes (word-rounded), 4N
-  for (int i = 0; i < c->ngroups; ++i) {
-    const GroupDesc& g = c->g[i];
-    if (g.V > 32768)
-      return fail(MUCA_EINVAL, "group %d: %d sites exceed the droplet measurement's 32768", i,
-                  g.V);
-    const size_t a = 2 * (size_t)g.V > 4 * (size_t)g.N ? (2 * (size_t)g.V + 3) / 4 * 4
-                                                          : 4 * (size_t)g.N;
-    need = std::max(need, a + 4 * (size_t)g.N);
-  }
-  if (need > c->lds_device)
-    return fail(MUCA_EINVAL, "droplet measurement needs %zu bytes of LDS per block", need);
-  // the kernel has no static LDS; allow exactly what this context needs
-  HIP_TRY(hipFuncSetAttribute((const void*)muca::k_largest_cluster,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+  const size_t need = droplet_lds(c);
+  if (!need) return MUCA_EINVAL;
+  if (int r = droplet_attr(need)) return r;
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
-  hipLaunchKernelGGL(muca::k_largest_cluster, dim3((unsigned)c->nwalkers), dim3(256), need, s,
-                     c->d_groups, c->d_wgroup, c->d_pos, out);
+  return enqueue_droplets(c, out, nullptr, nullptr, need, s);
+}
+
+int mucaMeasureDroplets(muca_ctx c, long long* osum, int32_t* ocount, int32_t* out,
+                        void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!osum || !ocount) return fail(MUCA_EINVAL, "osum and ocount must not be NULL");
+  const size_t need = droplet_lds(c);
+  if (!need) return MUCA_EINVAL;
+  if (int r = droplet_attr(need)) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  return enqueue_droplets(c, out, osum, ocount, need, s);
+}
+
+int mucaProduction(muca_ctx c, const double* lnW, int sweeps_between, int measurements,
+                   int32_t* H, long long* osum, int32_t* ocount, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW || !H || !osum || !ocount)
+    return fail(MUCA_EINVAL, "lnW, H, osum and ocount must not be NULL");
+  if (measurements < 1) return fail(MUCA_EINVAL, "measurements must be >= 1");
+  if (int r = check_sweeps(c, sweeps_between)) return r;
+  if ((int64_t)sweeps_between * measurements > 2147483647LL)
+    return fail(MUCA_EOVERFLOW, "sweeps_between x measurements exceeds INT32_MAX");
+  if (int r = check_sweeps(c, sweeps_between * measurements)) return r;
+  const size_t need = droplet_lds(c);
+  if (!need) return MUCA_EINVAL;
+  if (int r = droplet_attr(need)) return r;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const unsigned fill = (unsigned)std::min(1024, (c->total_bins + 255) / 256);
+  hipLaunchKernelGGL(muca::k_fill_i64, dim3(fill), dim3(256), 0, s, osum, 0LL, c->total_bins);
+  hipLaunchKernelGGL(muca::k_fill_i32, dim3(fill), dim3(256), 0, s, ocount, 0, c->total_bins);
+  LAUNCH_CHECK();
+  if (int r = enqueue_thresholds(c, lnW, s)) return r;
+  if (int r = enqueue_zero_hist(c, H, c->d_ones, s)) return r;
+  const int layout = resolved_layout(c);
+  for (int m = 0; m < measurements; ++m) {
+    if (int r = enqueue_sweep_kernel(c, layout, sweeps_between, H, c->d_ones, s)) return r;
+    if (int r = enqueue_droplets(c, nullptr, osum, ocount, need, s)) return r;
+  }
+  return MUCA_OK;
+}
+
+int mucaReweightObservable(muca_ctx c, const double* lnW, const int32_t* ocount,
+                           const long long* osum, const double* beta, int nbeta, double* out,
+                           void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW || !ocount || !osum || !beta || !out)
+    return fail(MUCA_EINVAL, "lnW, ocount, osum, beta and out must not be NULL");
+  if (nbeta < 1) return fail(MUCA_EINVAL, "nbeta must be >= 1, got %d", nbeta);
+  if ((int64_t)nbeta * c->ngroups > 0x7FFFFFFFLL)
+    return fail(MUCA_EINVAL, "ngroups x nbeta exceeds the grid limit");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  hipLaunchKernelGGL(muca::k_reweight_obs, dim3((unsigned)(c->ngroups * nbeta)), dim3(256), 0, s,
+                     c->d_groups, lnW, ocount, osum, beta, nbeta, out);
   LAUNCH_CHECK();
   return MUCA_OK;
 }

@@ -57,10 +57,12 @@ SIGNATURES = {
     "mucaGetWindow": (ctypes.c_int, [_vp, ctypes.c_int, _P(_i32), _P(_i32), _P(_i32)]),
     "mucaSetLayout": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaGetLayout": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
+    "mucaGetPlacement": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "mucaAutotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _P(ctypes.c_int),
                                     _P(ctypes.c_double), _vp]),
     "mucaSetLdsLimit": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "mucaSetGraph": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mucaSetResidentLimit": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "mucaThresholdEntries": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
     "mucaBuildThresholds": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaSweep": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
@@ -75,6 +77,9 @@ SIGNATURES = {
     "mucaSetTunnelTarget": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaReweight": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "mucaLargestCluster": (ctypes.c_int, [_vp, _vp, _vp]),
+    "mucaMeasureDroplets": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mucaProduction": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "mucaReweightObservable": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "mucaGetTunnel": (ctypes.c_int, [_vp, _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
     "mucaMlpParamCount": (ctypes.c_int, []),
     "mucaMlpCreate": (ctypes.c_int, [_P(_vp), ctypes.c_int]),
@@ -190,8 +195,17 @@ class Context:
     def layout(self):
         return self._int(lib().mucaGetLayout)
 
+    def placement(self):
+        """(walker state in LDS, threshold table in LDS) of the resolved layout."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().mucaGetPlacement(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), bool(b.value)
+
     def set_lds_limit(self, nbytes):
         _check(lib().mucaSetLdsLimit(self._h, int(nbytes)))
+
+    def set_resident_limit(self, nbytes):
+        _check(lib().mucaSetResidentLimit(self._h, int(nbytes)))
 
     def set_graph(self, enable):
         _check(lib().mucaSetGraph(self._h, 1 if enable else 0))
@@ -258,6 +272,35 @@ class Context:
         int32, nwalkers)."""
         _check(lib().mucaLargestCluster(self._h, _dev(out, torch.int32, self.nwalkers, "out"),
                                         _stream(stream)))
+
+    def measure_droplets(self, osum, ocount, out=None, stream=None):
+        """Add every walker's largest droplet to osum (device int64) at its
+        energy bin and count it in ocount (device int32)."""
+        o = None if out is None else _dev(out, torch.int32, self.nwalkers, "out")
+        _check(lib().mucaMeasureDroplets(self._h, _dev(osum, torch.int64, self.total_bins, "osum"),
+                                         _dev(ocount, torch.int32, self.total_bins, "ocount"), o,
+                                         _stream(stream)))
+
+    def production(self, lnW, sweeps_between, measurements, H, osum, ocount, stream=None):
+        """mucaProduction: rounds of sweeps and droplet measurements with
+        fixed weights."""
+        _check(lib().mucaProduction(self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
+                                    int(sweeps_between), int(measurements),
+                                    _dev(H, torch.int32, self.total_bins, "H"),
+                                    _dev(osum, torch.int64, self.total_bins, "osum"),
+                                    _dev(ocount, torch.int32, self.total_bins, "ocount"),
+                                    _stream(stream)))
+
+    def reweight_observable(self, lnW, ocount, osum, beta, out, stream=None):
+        """Canonical average of a measured observable per group and beta into
+        out (device float64, ngroups x len(beta))."""
+        nb = int(beta.numel())
+        _check(lib().mucaReweightObservable(
+            self._h, _dev(lnW, torch.float64, self.total_bins, "lnW"),
+            _dev(ocount, torch.int32, self.total_bins, "ocount"),
+            _dev(osum, torch.int64, self.total_bins, "osum"),
+            _dev(beta, torch.float64, nb, "beta"), nb,
+            _dev(out, torch.float64, self.ngroups * nb, "out"), _stream(stream)))
 
     def set_tunnel_target(self, target):
         _check(lib().mucaSetTunnelTarget(self._h, int(target)))

@@ -57,3 +57,28 @@ def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr
+
+
+def test_cpu_sample_is_a_prefix_of_the_walkers():
+    groups = [(3, 48, 3318, 16384)]
+    n = bench.sample_walkers(groups, 1e8)
+    assert n == 905  # ceil(1e8 / 48^3)
+    assert bench.first_walkers(groups, n) == [(3, 48, 3318, 905)]
+    mixed = [(2, 8, 16, 3), (3, 4, 6, 2, -10, 0), (2, 6, 9, 4)]
+    assert bench.first_walkers(mixed, 4) == [(2, 8, 16, 3), (3, 4, 6, 1, -10, 0)]
+    assert bench.sample_walkers(mixed, 1) == 1
+    assert bench.sample_walkers(mixed, 1e12) == 9
+
+
+def test_per_attempt_counts_follow_the_algorithm():
+    # 3D at rho = 0.03: Philox block (110), 3 draws (12), 12 neighbour indices
+    # (36), 12 bit tests (24), two 3D coordinate splits (24), decision (8)
+    assert abs(bench.valu_ops_per_attempt(3, 0.0) - 214.0) < 1e-9
+    assert abs(bench.valu_ops_per_attempt(2, 0.0) - 182.0) < 1e-9
+    # pos[k], candidate word, 2 x 2d neighbour words, threshold entry
+    assert abs(bench.state_bytes_per_attempt(3, 0.0) - 60.0) < 1e-9
+    assert abs(bench.state_bytes_per_attempt(2, 0.5) - 48.0) < 1e-9
+    g = [(3, 48, 3318, 10), (2, 8, 16, 10)]
+    mean = bench._weighted(g, bench.valu_ops_per_attempt)
+    lo, hi = bench.valu_ops_per_attempt(2, 0.25), bench.valu_ops_per_attempt(3, 0.03)
+    assert min(lo, hi) < mean < max(lo, hi)

@@ -1,6 +1,7 @@
 """GPU parity of the largest-droplet measurement (mucaLargestCluster, through
 the C ABI) against the oracle's breadth-first search on the same walker
-configurations (integer result: exact)."""
+configurations (integer result: exact), from small lattices to the large 3D
+workload (V = 110592 sites)."""
 import numpy as np
 import pytest
 
@@ -26,9 +27,12 @@ def _bits_to_occ(bits, V):
 
 
 def test_largest_cluster_matches_oracle():
-    # 2D and 3D, dense and sparse, a bricked 3D group, V = 32768 (the limit), N = 1
+    # 2D and 3D, dense and sparse, a bricked 3D group, V = 32768, N = 1, and
+    # particle counts at and next to powers of two (the LDS of the sorted
+    # sites is padded to one)
     groups = [(2, 8, 16, 4), (3, 5, 30, 3), (2, 32, 300, 3), (3, 16, 1300, 2),
-              (3, 24, 1100, 2), (3, 32, 655, 1), (2, 6, 1, 2)]
+              (3, 24, 1100, 2), (3, 32, 655, 1), (2, 6, 1, 2), (2, 16, 128, 3),
+              (2, 16, 127, 2), (2, 64, 1024, 1), (3, 16, 1025, 1), (3, 48, 3318, 1)]
     say("droplets", groups)
     ctx = M.Context(groups, seed=7)
     ref = O.RefContext(groups, seed=7)
@@ -73,9 +77,39 @@ def test_full_size_batched_2d_sampled():
         first += walkers
 
 
-def test_too_large_lattice_is_refused():
-    ctx = M.Context([(3, 48, 3318, 1)], seed=1)
-    out = torch.empty(1, dtype=torch.int32, device=DEV)
+def test_full_size_large_3d_sampled():
+    """The large 3D workload (V = 110592 sites, N = 3318, bricked state in
+    device memory): every walker measured, sampled walkers replayed by the
+    oracle's search."""
+    wl = W.WORKLOADS["large_3d"]
+    ctx = M.Context(wl["groups"], wl["seed"])
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+    ctx.sweep(torch.zeros(ctx.total_bins, dtype=torch.float64, device=DEV), 1, H)
+    out = torch.full((ctx.nwalkers,), -7, dtype=torch.int32, device=DEV)
+    ctx.largest_cluster(out)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    ctx.largest_cluster(out)
+    b.record()
+    torch.cuda.synchronize()
+    say(f"largest cluster: {ctx.nwalkers} walkers of V = 110592 in {a.elapsed_time(b):.3f} ms")
+    got = out.cpu().numpy()
+    d, L, N, walkers = wl["groups"][0]
+    assert ((got >= 1) & (got <= N)).all()
+    rng = np.random.default_rng(5)
+    for w in rng.choice(walkers, 6, replace=False):
+        bits, pos, E, t = ctx.read_walker(int(w))
+        assert got[w] == largest_cluster(_bits_to_occ(bits, L ** d), d, L), w
+    ctx.close()
+
+
+def test_too_many_particles_are_refused():
+    # N = 16500 sorted sites (padded to 32768) and parents exceed the LDS
+    ctx = M.Context([(3, 32, 16500, 1, -49500, 0)], seed=1)
+    out = torch.full((1,), -7, dtype=torch.int32, device=DEV)
     with pytest.raises(M.MucaError) as e:
         ctx.largest_cluster(out)
     assert e.value.code == M.MUCA_EINVAL
+    torch.cuda.synchronize()
+    assert out.item() == -7
