@@ -195,6 +195,22 @@ int mucaSweep(muca_ctx ctx, const double* lnW, int sweeps, int32_t* H, void* str
 int mucaSweepActive(muca_ctx ctx, const double* lnW, int sweeps, int32_t* H,
                     const int32_t* active, void* stream);
 
+/* mucaSweep for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sweep, with the same results and arguments, that calls no allocating
+ * routine.  Its threshold table and block task table live in a static device
+ * workspace of 4 MiB (MUCA_NOALLOC_WORKSPACE_BYTES) per device, set up when
+ * the first context is created on that device; the task table is the plain
+ * one (one set of walkers per block, sets in group order), written by a
+ * kernel on `stream`.  Fails with MUCA_EINVAL, before any device work, when
+ * the context's threshold table plus task table exceed the workspace (the
+ * threshold table holds total bins x (4d+1) 32-bit entries).  Every call on
+ * a device shares that device's workspace: calls that overlap in time on one
+ * device (different streams or host threads) race and must be serialised by
+ * the caller. */
+#define MUCA_NOALLOC_WORKSPACE_BYTES 4194304
+int mucaSweepNoAlloc(muca_ctx ctx, const double* lnW, int sweeps, int32_t* H, void* stream);
+
 /* Next weights from the previous weights and the summed histogram
  * (Sec. 2), in place on lnW and P (device pointers).  rule:
  *   MUCA_RULE_SIMPLE: lnW(b) -= ln max(H(b), 1), then lnW -= lnW(e_hi);

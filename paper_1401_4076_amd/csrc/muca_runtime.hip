@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -109,6 +110,59 @@ int dev_alloc(T** p, size_t n) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------- static workspace
+// Device memory of the allocation-free sweep (mucaSweepNoAlloc): the
+// threshold table, then the task table of the cooperative layouts.  One copy
+// per device, held until the process ends; every call on a device shares it.
+constexpr size_t kStaticBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Looks up the device address of the workspace on the current device (once
+// per device).  In host code `scratch` names a host-side stand-in, never the
+// device memory, so kernels and copies use only the address found here.
+int static_setup(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(MUCA_EHIP, "device %d beyond the %d supported", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_ptr[device]) return MUCA_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(MUCA_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_static_ptr[device] = ptr;
+  return MUCA_OK;
+}
+
+// The plain task table of a cooperative layout: set i is walkers
+// [f, f + count) of one group, sets in group order, one set per block.
+__global__ void k_plain_tasks(const GroupDesc* __restrict__ groups, int ngroups, int wpb,
+                              SweepTask* __restrict__ tasks, int32_t* __restrict__ first,
+                              int nsets) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) first[nsets] = nsets;
+  if (i >= nsets) return;
+  int base = 0;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const GroupDesc g = groups[gi];
+    const int n = (g.walkers + wpb - 1) / wpb;
+    if (i < base + n) {
+      const int f = (i - base) * wpb;
+      tasks[i] = SweepTask{gi, g.first_walker + f, min(wpb, g.walkers - f), 0};
+      first[i] = i;
+      return;
+    }
+    base += n;
+  }
+}
+
+}  // namespace
 
 namespace {
 
@@ -458,6 +512,10 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
   c->total_words = words;
   c->total_pos = pos;
   HIP_TRY_DEL(hipGetDevice(&c->device));
+  if (int r = static_setup(c->device)) {
+    delete c;
+    return r;
+  }
   {
     int v = 0;
     HIP_TRY_DEL(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
@@ -787,6 +845,70 @@ int mucaSweepActive(muca_ctx c, const double* lnW, int sweeps, int32_t* H, const
 
 int mucaSweep(muca_ctx c, const double* lnW, int sweeps, int32_t* H, void* stream) {
   return mucaSweepActive(c, lnW, sweeps, H, nullptr, stream);
+}
+
+int mucaSweepNoAlloc(muca_ctx c, const double* lnW, int sweeps, int32_t* H, void* stream) {
+  if (int r = check_ctx(c)) return r;
+  if (!lnW || !H) return fail(MUCA_EINVAL, "lnW and H must not be NULL");
+  if (int r = check_sweeps(c, sweeps)) return r;
+  unsigned char* ws = (unsigned char*)g_static_ptr[c->device];
+  if (!ws) return fail(MUCA_EHIP, "static workspace of device %d not set up", c->device);
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const int layout = resolved_layout(c);
+  // workspace: [thresholds][tasks][first], each 256-byte aligned
+  auto up = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  const size_t thr_bytes = up((size_t)c->thr_entries * sizeof(uint32_t));
+  int which = -1, G = 0;
+  switch (layout) {
+    case MUCA_LAYOUT_SUB16: which = 0; G = 16; break;
+    case MUCA_LAYOUT_SUB64: which = 1; G = 64; break;
+    case MUCA_LAYOUT_LOOK4: which = 4; G = 64; break;
+    case MUCA_LAYOUT_SUB16X2: which = 2; G = 16; break;
+    case MUCA_LAYOUT_SUB16X1: which = 3; G = 16; break;
+    default: break;  // MUCA_LAYOUT_LANE: no task table
+  }
+  int nsets = 0, wpb = 1;
+  if (which >= 0) {
+    wpb = 256 / kCoopLanes[which] / kCoopSpread[which];
+    for (const auto& g : c->g) nsets += (g.walkers + wpb - 1) / wpb;
+  }
+  const size_t task_bytes = which >= 0 ? up((size_t)nsets * sizeof(SweepTask)) : 0;
+  const size_t first_bytes = which >= 0 ? up(((size_t)nsets + 1) * sizeof(int32_t)) : 0;
+  if (thr_bytes + task_bytes + first_bytes > kStaticBytes)
+    return fail(MUCA_EINVAL,
+                "mucaSweepNoAlloc: this context needs %zu bytes of workspace (threshold table "
+                "%zu, tasks %zu), more than the static %zu",
+                thr_bytes + task_bytes + first_bytes, thr_bytes, task_bytes + first_bytes,
+                kStaticBytes);
+  uint32_t* thr = (uint32_t*)ws;
+  SweepTask* tasks = (SweepTask*)(ws + thr_bytes);
+  int32_t* first = (int32_t*)(ws + thr_bytes + task_bytes);
+  if (int r = enqueue_thresholds_to(c, lnW, thr, s)) return r;
+  if (int r = enqueue_zero_hist(c, H, c->d_ones, s)) return r;
+  if (which < 0) {
+    hipLaunchKernelGGL(muca::k_sweep_lane, dim3((unsigned)((c->nwalkers + 63) / 64)), dim3(64),
+                       0, s, c->d_groups, c->d_wgroup, c->d_bits, c->d_pos, c->d_E, c->d_T,
+                       c->d_tun, thr, H, c->d_ones, c->nwalkers, sweeps, c->first_id,
+                       c->seed32);
+    LAUNCH_CHECK();
+    return MUCA_OK;
+  }
+  hipLaunchKernelGGL(k_plain_tasks, dim3((unsigned)((nsets + 255) / 256)), dim3(256), 0, s,
+                     c->d_groups, c->ngroups, wpb, tasks, first, nsets);
+  LAUNCH_CHECK();
+  const size_t need = coop_sizes(c, which);
+  const CoopTables q{tasks, first, nsets, need, thr};
+  if (which == 4) {
+    if (look_fits(c, need)) {
+      launch_look_tables(c, tasks, nsets, need, thr, sweeps, H, c->d_ones, s);
+      LAUNCH_CHECK();
+      return MUCA_OK;
+    }
+    return launch_coop_tables<64>(c, 1, q, sweeps, H, c->d_ones, s);  // as SUB64
+  }
+  return G == 16 ? launch_coop_tables<16>(c, which, q, sweeps, H, c->d_ones, s)
+                 : launch_coop_tables<64>(c, which, q, sweeps, H, c->d_ones, s);
 }
 
 int mucaUpdateWeights(muca_ctx c, const int32_t* H, double* lnW, double* P, int rule,

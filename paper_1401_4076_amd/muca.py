@@ -35,6 +35,7 @@ MUCA_LAYOUT_LOOK4 = 4
 MUCA_LAYOUT_SUB16X2 = 5
 MUCA_LAYOUT_SUB16X1 = 6
 MUCA_NUM_LAYOUTS = 7
+MUCA_NOALLOC_WORKSPACE_BYTES = 4194304
 LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64, MUCA_LAYOUT_LOOK4,
            MUCA_LAYOUT_SUB16X2, MUCA_LAYOUT_SUB16X1)
 
@@ -67,6 +68,7 @@ SIGNATURES = {
     "mucaBuildThresholds": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaSweep": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "mucaSweepActive": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp]),
+    "mucaSweepNoAlloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "mucaUpdateWeights": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "mucaIsFlat": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaRun": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -232,6 +234,13 @@ class Context:
             a = _dev(active, torch.int32, self.ngroups, "active")
             _check(lib().mucaSweepActive(self._h, p, int(sweeps), h, a, _stream(stream)))
 
+    def sweep_noalloc(self, lnW, sweeps, H, stream=None):
+        """mucaSweepNoAlloc: the sweep with its tables in the library's static
+        device workspace (no allocation in the call)."""
+        p = _dev(lnW, torch.float64, self.total_bins, "lnW")
+        h = _dev(H, torch.int32, self.total_bins, "H")
+        _check(lib().mucaSweepNoAlloc(self._h, p, int(sweeps), h, _stream(stream)))
+
     def update_weights(self, H, lnW, P, rule=MUCA_RULE_BERG, stream=None):
         _check(lib().mucaUpdateWeights(self._h, _dev(H, torch.int32, self.total_bins, "H"),
                                        _dev(lnW, torch.float64, self.total_bins, "lnW"),
@@ -348,6 +357,10 @@ def mucaInit(d, L, N, walkers, seed):
 
 def mucaSweep(ctx, lnW, sweeps, H, stream=None):
     ctx.sweep(lnW, sweeps, H, stream=stream)
+
+
+def mucaSweepNoAlloc(ctx, lnW, sweeps, H, stream=None):
+    ctx.sweep_noalloc(lnW, sweeps, H, stream=stream)
 
 
 def mucaSweepActive(ctx, lnW, sweeps, H, active, stream=None):
