@@ -71,6 +71,64 @@ def flat_detail(ctx, H):
     return out
 
 
+def race(groups, seed, sweeps, max_iters, lnW0=None, tunnel_target=30, rule=M.MUCA_RULE_BERG,
+         max_seconds=None, progress=None, extra_seconds=0.0):
+    """The iteration one step at a time (fixed schedule, mucaRun resumed per
+    iteration), noting when each stop criterion is first met: the paper's
+    convergence at `tunnel_target` tunnelling events in total (Sec. 4) and a
+    flat histogram (every group).  Stops when both are met, after max_iters
+    iterations or once max_seconds have passed.  Per iteration: elapsed
+    seconds (plus extra_seconds, e.g. the network's inference), tunnelling
+    events, flatness and flat_detail of H^i.  Returns the trajectory, the
+    first iteration and time of each criterion (None if not met) and
+    ln Omega = ln H^i - ln W^i of the last iteration (host arrays per group)."""
+    ctx = M.Context(groups, seed)
+    ctx.set_tunnel_target(tunnel_target)
+    dev = torch.device("cuda")
+    lnW = (torch.zeros(ctx.total_bins, dtype=torch.float64, device=dev) if lnW0 is None
+           else lnW0.clone())
+    P = torch.zeros_like(lnW)
+    H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
+    prev = torch.empty_like(lnW)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    traj, first_flat, first_tunnel = [], None, None
+    for i in range(max_iters):
+        prev.copy_(lnW)  # the weights that produce H^i
+        _, _, fl = ctx.run(lnW, P, H, sweeps, 1, rule, stop=M.MUCA_STOP_NONE, resume=i > 0)
+        sec = time.perf_counter() - t0 + extra_seconds
+        trips = int(sum(ctx.tunnel()[1]))
+        flat = all(fl)
+        rec = {"iter": i + 1, "seconds": round(sec, 2), "tunnelling": trips, "flat": flat,
+               "detail": flat_detail(ctx, H)}
+        traj.append(rec)
+        if flat and first_flat is None:
+            first_flat = {"iter": i + 1, "seconds": sec}
+        if trips >= tunnel_target and first_tunnel is None:
+            first_tunnel = {"iter": i + 1, "seconds": sec}
+        if progress:
+            progress(rec)
+        if first_flat and first_tunnel:
+            break
+        if max_seconds is not None and sec > max_seconds:
+            break
+    lo = ln_omega(ctx, prev, H)
+    ctx.close()
+    return {"trajectory": traj, "first_flat": first_flat, "first_tunnel": first_tunnel,
+            "iterations": len(traj), "ln_omega": lo}
+
+
+def ln_omega_difference(a, b):
+    """Largest |difference| of two ln Omega estimates of one group over the
+    bins both visited, after removing the mean offset; and the bin count."""
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    both = ~np.isnan(a) & ~np.isnan(b)
+    if not both.any():
+        return float("nan"), 0
+    d = a[both] - b[both]
+    return float(np.max(np.abs(d - d.mean()))), int(both.sum())
+
+
 def table_rows(ctx, lnW, groups=None):
     """Features and targets of every bin of the chosen groups (all by default)."""
     sel = range(ctx.ngroups) if groups is None else groups

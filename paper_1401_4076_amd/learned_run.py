@@ -58,6 +58,11 @@ def main():
     ap.add_argument("--net", default=None, help="parameter file (.npy) to save or load")
     ap.add_argument("--max-seconds", type=float, default=None,
                     help="wall-time budget of each iteration run (stops between chunks)")
+    ap.add_argument("--race", action="store_true",
+                    help="eval: step the iteration one at a time under a shared cap and note "
+                         "when the tunnelling target and flatness are first met (see learned.race)")
+    ap.add_argument("--tunnel-target", type=int, default=30)
+    ap.add_argument("--out", default=None, help="eval --race: JSON file rewritten every iteration")
     args = ap.parse_args()
     if args.stage != "all" and not args.net:
         ap.error("--stage train/eval needs --net")
@@ -127,7 +132,52 @@ def train_stage(args, out):
     return net
 
 
+def race_stage(args, net, out):
+    """Each arm on the target under the same seeds, sweeps and caps."""
+    wl = W.scaled(args.target, walkers_per_group=args.target_walkers, sweeps=args.target_sweeps)
+    out.update({"target": args.target, "target_groups": [list(g) for g in wl["groups"]],
+                "target_sweeps": wl["sweeps"], "cap_iterations": args.target_max_iters,
+                "cap_seconds": args.max_seconds, "tunnel_target": args.tunnel_target,
+                "seed": wl["seed"], "arms": {}})
+    log(f"race on {args.target}: groups {wl['groups']} sweeps {wl['sweeps']}")
+
+    def dump():
+        if args.out:
+            with open(args.out + ".tmp", "w") as f:
+                json.dump(out, f)
+            os.replace(args.out + ".tmp", args.out)
+
+    for arm in args.arms.split(","):
+        t0 = time.perf_counter()
+        lnW0 = None
+        if arm == "learned":
+            probe = M.Context(wl["groups"], wl["seed"])
+            lnW0 = LR.predict(net, probe)
+            probe.close()
+        infer = time.perf_counter() - t0  # the learned arm includes the network's inference
+        rec = out["arms"].setdefault(arm, {"inference_seconds": infer, "trajectory": []})
+
+        def progress(r, _rec=rec, _arm=arm):
+            _rec["trajectory"].append(r)
+            d = r["detail"][0]
+            log(f"  {_arm}: iteration {r['iter']}, {r['seconds']:.1f} s, tunnelling "
+                f"{r['tunnelling']}, flat {r['flat']}, (bottom, top visited, min/max, lowest E, "
+                f"visited) {d}")
+            dump()
+
+        res = LR.race(wl["groups"], wl["seed"], wl["sweeps"], args.target_max_iters, lnW0=lnW0,
+                      tunnel_target=args.tunnel_target, max_seconds=args.max_seconds,
+                      progress=progress, extra_seconds=infer)
+        rec.update({k: res[k] for k in ("first_flat", "first_tunnel", "iterations")})
+        rec["ln_omega"] = [[None if np.isnan(x) else float(x) for x in v]
+                           for v in res["ln_omega"]]
+        dump()
+
+
 def eval_stage(args, net, out):
+    if args.race:
+        race_stage(args, net, out)
+        return
     out["target"] = args.target
     wl = W.scaled(args.target, walkers_per_group=args.target_walkers, sweeps=args.target_sweeps)
     out["target_groups"] = [list(g) for g in wl["groups"]]
