@@ -228,6 +228,9 @@ def main():
                          "3 64 lanes/walker, 4 lookahead, 5/6 16 lanes with 2/1 walkers "
                          "per wavefront)")
     ap.add_argument("--probe-sweeps", type=int, default=1, help="autotune probe length")
+    ap.add_argument("--resident-mib", type=int, default=None,
+                    help="with --layout: cap of the walker state in flight when it lives in "
+                         "device memory (MiB, 0 = none; default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
@@ -259,6 +262,8 @@ def main():
               file=sys.stderr, flush=True)
     else:
         ctx.set_layout(args.layout)
+        if args.resident_mib is not None:
+            ctx.set_resident_limit(args.resident_mib << 20)
     state_lds, table_lds = ctx.placement()
     P = torch.zeros_like(lnW)
     H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
@@ -335,6 +340,7 @@ def main():
                    "walkers": sum(g[3] for g in groups), "sweeps_per_iter": sweeps,
                    "attempts_per_step": per_step, "rule": "berg", "layout": ctx.layout(),
                    "state_in_lds": state_lds, "table_in_lds": table_lds,
+                   "resident_limit_bytes": ctx.resident_limit(),
                    "autotune_probe_ms": tune_ms},
         "sweep_kernel_ms": sweep_ms,
         "roofline": roof,

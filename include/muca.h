@@ -152,9 +152,10 @@ int mucaSetLdsLimit(muca_ctx ctx, int64_t bytes);
  * memory: the walker sets then run in rounds of whole blocks per compute
  * unit, at least one block per compute unit.  The random accesses of the
  * sweep are cheapest while the state in flight fits the device's last-level
- * cache (256 MB on MI355X).  Default 224 MiB; 0 = no cap.  Results are
- * unchanged; only the speed differs. */
+ * cache (256 MB on MI355X).  Default 224 MiB; 0 = no cap; mucaAutotune may
+ * change it (see there).  Results are unchanged; only the speed differs. */
 int mucaSetResidentLimit(muca_ctx ctx, int64_t bytes);
+int mucaGetResidentLimit(muca_ctx ctx, int64_t* bytes);
 
 /* Time every layout on `probe_sweeps` sweeps with weights lnW (device) and
  * keep the fastest; a cooperative layout whose walker state lives in device

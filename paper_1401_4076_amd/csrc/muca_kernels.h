@@ -17,7 +17,7 @@ __global__ void k_sweep_lane(const GroupDesc* groups, const int32_t* wgroup, uin
                              const uint32_t* thr,
                              int32_t* H, const int32_t* active, int nwalkers, int sweeps,
                              uint32_t first_id, uint32_t seed32);
-template <int G, bool kLds, bool kTbl, bool kPipe>
+template <int G, bool kLds, bool kTbl, int kPipe>
 __global__ void k_sweep_sub(const GroupDesc* groups, const SweepTask* tasks, const int32_t* first,
                             uint32_t* gbits, uint32_t* gpos, int32_t* gE, uint64_t* gT,
                             uint32_t* gtun, const uint32_t* thr, int32_t* H,

@@ -324,16 +324,22 @@ int launch_coop_tables(muca_ctx c, int which, const CoopTables& q, int sweeps, i
   const bool tbl_lds = c->lds_limit > 0 && state + c->tbl_bytes <= cap;
   const size_t dyn = state + (tbl_lds ? c->tbl_bytes : 0);
   const int tbl_words = tbl_lds ? (int)(c->tbl_bytes / sizeof(uint32_t)) : 0;
-  // With state in device memory the 16-lane layouts issue the next attempt's
-  // gather before deciding the current one (kPipe); the 64-lane layout does
-  // not (pipelined, it ran slower on the large 3D lattices).
+  // With state in device memory the 16-lane layouts issue the gathers of the
+  // next attempts before deciding the current one: two ahead when every
+  // group's V is a multiple of 16 (full batches), else one; the 64-lane
+  // layout does not pipeline (pipelined, it ran slower on the large 3D
+  // lattices).
   const bool pipe = G == 16;
-  auto kern = state_lds ? (tbl_lds ? muca::k_sweep_sub<G, true, true, false>
-                                   : muca::k_sweep_sub<G, true, false, false>)
-            : pipe      ? (tbl_lds ? muca::k_sweep_sub<16, false, true, true>
-                                   : muca::k_sweep_sub<16, false, false, true>)
-                        : (tbl_lds ? muca::k_sweep_sub<64, false, true, false>
-                                   : muca::k_sweep_sub<64, false, false, false>);
+  bool full16 = true;
+  for (const auto& g : c->g) full16 = full16 && g.V % 16 == 0;
+  auto kern = state_lds ? (tbl_lds ? muca::k_sweep_sub<G, true, true, 0>
+                                   : muca::k_sweep_sub<G, true, false, 0>)
+            : pipe      ? (full16 ? (tbl_lds ? muca::k_sweep_sub<16, false, true, 2>
+                                             : muca::k_sweep_sub<16, false, false, 2>)
+                                  : (tbl_lds ? muca::k_sweep_sub<16, false, true, 1>
+                                             : muca::k_sweep_sub<16, false, false, 1>))
+                        : (tbl_lds ? muca::k_sweep_sub<64, false, true, 0>
+                                   : muca::k_sweep_sub<64, false, false, 0>);
   hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.tasks,
                      q.first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, q.thr, H, active,
                      sweeps, c->first_id, c->seed32, tbl_words,
@@ -526,14 +532,16 @@ int mucaInitGroups(muca_ctx* out, const muca_group* groups, int ngroups, uint64_
     // allow every cooperative kernel the device's full LDS per block (set
     // once here, outside any stream capture)
     const void* kernels[] = {
-        (const void*)muca::k_sweep_sub<16, true, true, false>,
-        (const void*)muca::k_sweep_sub<16, true, false, false>,
-        (const void*)muca::k_sweep_sub<16, false, true, true>,
-        (const void*)muca::k_sweep_sub<16, false, false, true>,
-        (const void*)muca::k_sweep_sub<64, true, true, false>,
-        (const void*)muca::k_sweep_sub<64, true, false, false>,
-        (const void*)muca::k_sweep_sub<64, false, true, false>,
-        (const void*)muca::k_sweep_sub<64, false, false, false>,
+        (const void*)muca::k_sweep_sub<16, true, true, 0>,
+        (const void*)muca::k_sweep_sub<16, true, false, 0>,
+        (const void*)muca::k_sweep_sub<16, false, true, 1>,
+        (const void*)muca::k_sweep_sub<16, false, false, 1>,
+        (const void*)muca::k_sweep_sub<16, false, true, 2>,
+        (const void*)muca::k_sweep_sub<16, false, false, 2>,
+        (const void*)muca::k_sweep_sub<64, true, true, 0>,
+        (const void*)muca::k_sweep_sub<64, true, false, 0>,
+        (const void*)muca::k_sweep_sub<64, false, true, 0>,
+        (const void*)muca::k_sweep_sub<64, false, false, 0>,
         (const void*)muca::k_sweep_look<true>, (const void*)muca::k_sweep_look<false>};
     for (const void* k : kernels)
       HIP_TRY_DEL(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v));
@@ -801,6 +809,13 @@ int mucaSetLdsLimit(muca_ctx c, int64_t bytes) {
     c->lds_limit = (size_t)bytes;
     c->drop_tables();
   }
+  return MUCA_OK;
+}
+
+int mucaGetResidentLimit(muca_ctx c, int64_t* bytes) {
+  if (int r = check_ctx(c)) return r;
+  if (!bytes) return fail(MUCA_EINVAL, "null output");
+  *bytes = (int64_t)c->resident_limit;
   return MUCA_OK;
 }
 

@@ -26,8 +26,8 @@
 // and sites stay in device memory (workgroup-coherent accesses, the group's
 // bit layout: linear or bricked, see bit_ref) and the coordinates of s_o are
 // recomputed in the batch phase.  kPipe (device memory only; the 16-lane
-// layouts): the gather of the next attempt is issued before the current one
-// is decided.
+// layouts): the gathers of the next kPipe attempts (1 or 2) are issued before
+// the current one is decided.
 // spread (16 lanes only): walkers sit in every spread-th 16-lane row, so a
 // small population fills more wavefronts (layouts SUB16X2, SUB16X1).
 #include "muca_kernels.h"
@@ -196,8 +196,10 @@ struct Walker {
   // moves two values: (k, u), (c2, c2x), (c3, c3x), (s_o, s_o coordinates)
   uint64_t b_ku, b_c2p, b_c3p, b_sop;
   // device-memory path: the previous attempt's move (particle, old and new
-  // site; kNone if rejected) and the fetch of the next batch's first attempt
+  // site; kNone if rejected), the one before it (pm2_*, read by the two-deep
+  // pipeline) and the fetch of the next batch's first attempt
   uint32_t pm_k, pm_so, pm_sn, pm_snx;
+  uint32_t pm2_k, pm2_so, pm2_sn, pm2_snx;
   Pend next;
 };
 
@@ -297,6 +299,10 @@ __device__ __forceinline__ void resolve(Walker<G, kLds, kTbl>& W, uint32_t k, ui
     if (acc) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   }
   if constexpr (!kLds) {
+    W.pm2_k = W.pm_k;
+    W.pm2_so = W.pm_so;
+    W.pm2_sn = W.pm_sn;
+    W.pm2_snx = W.pm_snx;
     W.pm_k = acc ? k : kNone;
     W.pm_so = acc ? so : kNone;
     W.pm_sn = acc ? sn : kNone;
@@ -381,15 +387,27 @@ __device__ __forceinline__ Pend fetch64(const Walker<G, kLds, kTbl>& W, int a) {
   return p;
 }
 
-template <int G, bool kLds, bool kTbl>
+// Decision of a fetched attempt.  Its gather was issued D decisions earlier
+// (D = 1 or 2), so the moves of those D attempts (pm2_* the older, pm_* the
+// newer) are applied to the gathered bits, oldest first; if one of them moved
+// this attempt's particle, its neighbourhood is read again from the new site.
+template <int D, int G, bool kLds, bool kTbl>
 __device__ __forceinline__ void decide(Walker<G, kLds, kTbl>& W, Pend p, uint64_t ta) {
   const uint64_t ok = __ballot(p.u < W.Trow) | __ballot(W.Trow == kAlways);  // as in attempt()
   uint32_t bit = bit_at(p.v, p.sh);
+  if constexpr (D == 2) bit = (p.site == W.pm2_sn) ? 1u : ((p.site == W.pm2_so) ? 0u : bit);
   bit = (p.site == W.pm_sn) ? 1u : ((p.site == W.pm_so) ? 0u : bit);
-  const bool moved = p.k == W.pm_k;
+  const bool moved1 = p.k == W.pm_k;
+  bool moved = moved1;
+  if constexpr (D == 2) moved = moved1 || (p.k == W.pm2_k);
   if (__ballot(moved) != 0ull) {
-    p.so = moved ? W.pm_sn : p.so;
-    p.sox = moved ? W.pm_snx : p.sox;
+    uint32_t nso = W.pm_sn, nsox = W.pm_snx;
+    if constexpr (D == 2) {
+      nso = moved1 ? W.pm_sn : W.pm2_sn;
+      nsox = moved1 ? W.pm_snx : W.pm2_snx;
+    }
+    p.so = moved ? nso : p.so;
+    p.sox = moved ? nsox : p.sox;
     BitRef at;
     const uint32_t site = gather_site(W, p.so, p.sox, p.c2, p.c2x, p.c3, p.c3x, at);
     const uint32_t v = ld<kLds>(&W.bits[at.word]);
@@ -410,8 +428,22 @@ __device__ __forceinline__ Pend run16(Walker<G, kLds, kTbl>& W, Pend cur, int nb
   } else {
     if (A + 1 == nb) return cur;
     const Pend nxt = fetch16<A + 1, G, kLds, kTbl>(W);
-    decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)A);
+    decide<1, G, kLds, kTbl>(W, cur, W.t + (uint64_t)A);
     return run16<A + 1, G, kLds, kTbl>(W, nxt, nb);
+  }
+}
+
+// Two-deep pipeline over a full batch of 16: attempt A is decided after the
+// gather of A + 2 is issued.  a, b hold the fetches of attempts A and A + 1;
+// on return they hold those of attempts 14 and 15, still undecided.
+template <int A, int G, bool kLds, bool kTbl>
+__device__ __forceinline__ void run16x2(Walker<G, kLds, kTbl>& W, Pend& a, Pend& b) {
+  if constexpr (A < 14) {
+    const Pend c = fetch16<A + 2, G, kLds, kTbl>(W);
+    decide<2, G, kLds, kTbl>(W, a, W.t + (uint64_t)A);
+    a = b;
+    b = c;
+    run16x2<A + 1, G, kLds, kTbl>(W, a, b);
   }
 }
 
@@ -429,7 +461,10 @@ __device__ __forceinline__ void unrolled16(Walker<G, kLds, kTbl>& W, int nb) {
 }
 
 // One set of walkers (one task) for `sweeps` sweeps, by the whole block.
-template <int G, bool kLds, bool kTbl, bool kPipe>
+// kPipe: 0 = each attempt decided after its own gather (LDS state, or the
+// 64-lane layout), 1 or 2 = that many gathers ahead (device-memory state,
+// 16 lanes; 2 needs every group's V to be a multiple of 16).
+template <int G, bool kLds, bool kTbl, int kPipe>
 __device__ __forceinline__ void run_set(
     const GroupDesc* __restrict__ groups, const SweepTask task, uint32_t* smem,
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
@@ -510,7 +545,7 @@ __device__ __forceinline__ void run_set(
     // A batch never straddles the end of a sweep (the last batch of a sweep
     // may be short; its spare lanes compute attempts that the next batch
     // redoes), so the histogram entry is taken after the batch.
-    if constexpr (!kPipe) {
+    if constexpr (kPipe == 0) {
       for (int sw = 0; sw < sweeps; ++sw) {
         for (uint32_t done = 0; done < W.V; done += G) {
           const int nb = (int)((W.V - done) < (uint32_t)G ? (W.V - done) : (uint32_t)G);
@@ -535,9 +570,36 @@ __device__ __forceinline__ void run_set(
         if (ls == 0) atomicAdd(&W.hist[W.E], 1);
         W.tun = tunnel_step(W.tun, W.E, g.nbins - 1);
       }
+    } else if constexpr (kPipe == 2) {
+      static_assert(G == 16, "the two-deep pipeline is for 16 lanes per walker");
+      W.pm_k = W.pm_so = W.pm_sn = W.pm2_k = W.pm2_so = W.pm2_sn = kNone;
+      W.pm_snx = W.pm2_snx = 0u;
+      batch_phase<G, kLds>(W, W.t);
+      Pend a = fetch16<0, G, kLds, kTbl>(W);
+      Pend b = fetch16<1, G, kLds, kTbl>(W);
+      for (int sw = 0; sw < sweeps; ++sw) {
+        for (uint32_t done = 0; done < W.V; done += 16) {  // V % 16 == 0: full batches
+          const bool more = (done + 16u < W.V) || (sw + 1 < sweeps);
+          run16x2<0, G, kLds, kTbl>(W, a, b);  // attempts 0..13; a, b = 14, 15
+          Pend n0 = a, n1 = b;
+          // the next batch's values, then its first gathers, ahead of 14 and 15
+          if (more) {
+            batch_phase<G, kLds>(W, W.t + 16u);
+            n0 = fetch16<0, G, kLds, kTbl>(W);
+          }
+          decide<2, G, kLds, kTbl>(W, a, W.t + 14u);
+          if (more) n1 = fetch16<1, G, kLds, kTbl>(W);
+          decide<2, G, kLds, kTbl>(W, b, W.t + 15u);
+          W.t += 16u;
+          a = n0;
+          b = n1;
+        }
+        if (ls == 0) atomicAdd(&W.hist[W.E], 1);
+        W.tun = tunnel_step(W.tun, W.E, g.nbins - 1);
+      }
     } else {
-      W.pm_k = W.pm_so = W.pm_sn = kNone;
-      W.pm_snx = 0u;
+      W.pm_k = W.pm_so = W.pm_sn = W.pm2_k = W.pm2_so = W.pm2_sn = kNone;
+      W.pm_snx = W.pm2_snx = 0u;
       batch_phase<G, kLds>(W, W.t);
       if constexpr (G == 16) W.next = fetch16<0, G, kLds, kTbl>(W);
       else W.next = fetch64<G, kLds, kTbl>(W, 0);
@@ -552,7 +614,7 @@ __device__ __forceinline__ void run_set(
             cur = W.next;
             for (int a = 0; a + 1 < nb; ++a) {
               const Pend nxt = fetch64<G, kLds, kTbl>(W, a + 1);
-              decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)a);
+              decide<1, G, kLds, kTbl>(W, cur, W.t + (uint64_t)a);
               cur = nxt;
             }
           }
@@ -562,7 +624,7 @@ __device__ __forceinline__ void run_set(
             if constexpr (G == 16) W.next = fetch16<0, G, kLds, kTbl>(W);
             else W.next = fetch64<G, kLds, kTbl>(W, 0);
           }
-          decide<G, kLds, kTbl>(W, cur, W.t + (uint64_t)(nb - 1));
+          decide<1, G, kLds, kTbl>(W, cur, W.t + (uint64_t)(nb - 1));
           W.t += (uint64_t)nb;
         }
         if (ls == 0) atomicAdd(&W.hist[W.E], 1);
@@ -590,7 +652,7 @@ __device__ __forceinline__ void run_set(
 }  // namespace
 
 // Block b runs tasks [first[b], first[b + 1]) one after the other.
-template <int G, bool kLds, bool kTbl, bool kPipe>
+template <int G, bool kLds, bool kTbl, int kPipe>
 __global__ void __launch_bounds__(256) k_sweep_sub(
     const GroupDesc* __restrict__ groups, const SweepTask* __restrict__ tasks,
     const int32_t* __restrict__ first, uint32_t* __restrict__ gbits,
@@ -600,6 +662,7 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     int tbl_words, int hist_words, int spread) {
   static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
   static_assert(!(kLds && kPipe), "the pipelined gather is for device-memory state");
+  static_assert(kPipe >= 0 && kPipe <= 2 && (G == 16 || kPipe == 0), "pipeline depth");
   // LDS: [threshold table (tbl_words)] [block histogram (hist_words, LDS-state mode)]
   //      [walker slots]
   extern __shared__ uint32_t smem[];
@@ -612,35 +675,43 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   }
 }
 
-template __global__ void k_sweep_sub<16, true, true, false>(
+template __global__ void k_sweep_sub<16, true, true, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<16, true, false, false>(
+template __global__ void k_sweep_sub<16, true, false, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<16, false, true, true>(
+template __global__ void k_sweep_sub<16, false, true, 1>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<16, false, false, true>(
+template __global__ void k_sweep_sub<16, false, false, 1>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<64, true, true, false>(
+template __global__ void k_sweep_sub<16, false, true, 2>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<64, true, false, false>(
+template __global__ void k_sweep_sub<16, false, false, 2>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<64, false, true, false>(
+template __global__ void k_sweep_sub<64, true, true, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);
-template __global__ void k_sweep_sub<64, false, false, false>(
+template __global__ void k_sweep_sub<64, true, false, 0>(
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
+template __global__ void k_sweep_sub<64, false, true, 0>(
+    const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
+    uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
+    int, int);
+template __global__ void k_sweep_sub<64, false, false, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
     int, int);

@@ -64,6 +64,7 @@ SIGNATURES = {
     "mucaSetLdsLimit": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "mucaSetGraph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaSetResidentLimit": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "mucaGetResidentLimit": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "mucaThresholdEntries": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
     "mucaBuildThresholds": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mucaSweep": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
@@ -208,6 +209,11 @@ class Context:
 
     def set_resident_limit(self, nbytes):
         _check(lib().mucaSetResidentLimit(self._h, int(nbytes)))
+
+    def resident_limit(self):
+        v = ctypes.c_int64()
+        _check(lib().mucaGetResidentLimit(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_graph(self, enable):
         _check(lib().mucaSetGraph(self._h, 1 if enable else 0))

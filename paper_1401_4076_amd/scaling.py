@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--max-seconds", type=float, default=None, help="per p, between iterations")
     ap.add_argument("--out", default=None, help="JSON file rewritten after every p")
+    ap.add_argument("--first-id", type=int, default=0,
+                    help="first global walker id of the first p (a study split over several "
+                         "invocations continues the ranges of the earlier ones)")
     args = ap.parse_args()
 
     ps = [int(x) for x in args.p.split(",")]
@@ -148,7 +151,7 @@ def main():
            "seed": args.seed, "results": []}
     log(f"scaling: d={args.d} L={args.L} N={args.N} window [{lo}, {hi}], runs {args.runs}, "
         f"{args.total_sweeps} sweeps per iteration, target {args.target}")
-    first = 0
+    first = args.first_id
     for p in ps:
         res = runs_for(args.d, args.L, args.N, p, args.runs, args.seed, args.total_sweeps,
                        args.target, args.max_iters, args.rule, first_id=first,
