@@ -153,7 +153,9 @@ int mucaSetLdsLimit(muca_ctx ctx, int64_t bytes);
  * unit, at least one block per compute unit.  The random accesses of the
  * sweep are cheapest while the state in flight fits the device's last-level
  * cache (256 MB on MI355X).  Default 224 MiB; 0 = no cap; mucaAutotune may
- * change it (see there).  Results are unchanged; only the speed differs. */
+ * change it (see there).  Results are unchanged; only the speed differs.
+ * Changing this limit or the LDS limit waits for the device and rebuilds the
+ * context's task tables and captured iteration on their next use. */
 int mucaSetResidentLimit(muca_ctx ctx, int64_t bytes);
 int mucaGetResidentLimit(muca_ctx ctx, int64_t* bytes);
 

@@ -203,6 +203,19 @@ constexpr int kCoopLanes[5] = {16, 64, 16, 16, 64};  // lanes per walker
 constexpr int kCoopSpread[5] = {1, 1, 2, 4, 1};      // 16-lane rows per walker row used
 constexpr bool kCoopPacked[5] = {true, true, true, true, false};
 
+// Task table (coop index) of a cooperative layout, -1 for the one-walker-per-
+// lane layout.
+int coop_index(int layout) {
+  switch (layout) {
+    case MUCA_LAYOUT_SUB16: return 0;
+    case MUCA_LAYOUT_SUB64: return 1;
+    case MUCA_LAYOUT_SUB16X2: return 2;
+    case MUCA_LAYOUT_SUB16X1: return 3;
+    case MUCA_LAYOUT_LOOK4: return 4;
+    default: return -1;
+  }
+}
+
 // Host-side sizes of a cooperative layout: LDS bytes for the walker state of
 // the largest set (need), and the context's largest histogram and threshold
 // table of one group (hist_bytes, tbl_bytes).  No device work.
@@ -718,9 +731,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
     for (int lay = MUCA_LAYOUT_LANE; lay < MUCA_NUM_LAYOUTS; ++lay) {
       // cooperative layouts with walker state in device memory: with the
       // resident cap and without it
-      const int which = lay == MUCA_LAYOUT_SUB16 ? 0 : lay == MUCA_LAYOUT_SUB64 ? 1
-                      : lay == MUCA_LAYOUT_LOOK4 ? 4 : lay == MUCA_LAYOUT_SUB16X2 ? 2
-                      : lay == MUCA_LAYOUT_SUB16X1 ? 3 : -1;
+      const int which = coop_index(lay);
       const size_t capb = std::min(c->lds_limit, c->lds_device);
       const bool dev_state =
           which >= 0 && (c->bricked || coop_sizes(c, which) + c->hist_bytes > capb);
@@ -773,16 +784,7 @@ int mucaAutotune(muca_ctx c, const double* lnW, int probe_sweeps, int* chosen, d
 
 int mucaGetPlacement(muca_ctx c, int* state_in_lds, int* table_in_lds) {
   if (int r = check_ctx(c)) return r;
-  const int layout = resolved_layout(c);
-  int which = -1;
-  switch (layout) {
-    case MUCA_LAYOUT_SUB16: which = 0; break;
-    case MUCA_LAYOUT_SUB64: which = 1; break;
-    case MUCA_LAYOUT_LOOK4: which = 4; break;
-    case MUCA_LAYOUT_SUB16X2: which = 2; break;
-    case MUCA_LAYOUT_SUB16X1: which = 3; break;
-    default: break;
-  }
+  const int which = coop_index(resolved_layout(c));
   int st = 0, tb = 0;
   if (which >= 0) {
     const size_t need = coop_sizes(c, which);
@@ -874,15 +876,8 @@ int mucaSweepNoAlloc(muca_ctx c, const double* lnW, int sweeps, int32_t* H, void
   // workspace: [thresholds][tasks][first], each 256-byte aligned
   auto up = [](size_t n) { return (n + 255) & ~(size_t)255; };
   const size_t thr_bytes = up((size_t)c->thr_entries * sizeof(uint32_t));
-  int which = -1, G = 0;
-  switch (layout) {
-    case MUCA_LAYOUT_SUB16: which = 0; G = 16; break;
-    case MUCA_LAYOUT_SUB64: which = 1; G = 64; break;
-    case MUCA_LAYOUT_LOOK4: which = 4; G = 64; break;
-    case MUCA_LAYOUT_SUB16X2: which = 2; G = 16; break;
-    case MUCA_LAYOUT_SUB16X1: which = 3; G = 16; break;
-    default: break;  // MUCA_LAYOUT_LANE: no task table
-  }
+  const int which = coop_index(layout);  // -1: one walker per lane, no task table
+  const int G = which >= 0 ? kCoopLanes[which] : 0;
   int nsets = 0, wpb = 1;
   if (which >= 0) {
     wpb = 256 / kCoopLanes[which] / kCoopSpread[which];
