@@ -75,7 +75,10 @@ extern "C" {
                                  state in device memory the next attempt's gather
                                  is issued before the current one is decided */
 #define MUCA_LAYOUT_SUB16X1 6 /* as SUB16X2 with 1 walker per wavefront */
-#define MUCA_NUM_LAYOUTS 7    /* layout indices 0 .. MUCA_NUM_LAYOUTS - 1 */
+#define MUCA_LAYOUT_SUB16MIX 7 /* 16 lanes per walker, per group: 2 walkers per
+                                  wavefront for the groups with the context's
+                                  largest lattice, 4 for the others */
+#define MUCA_NUM_LAYOUTS 8    /* layout indices 0 .. MUCA_NUM_LAYOUTS - 1 */
 
 typedef struct muca_context* muca_ctx;
 

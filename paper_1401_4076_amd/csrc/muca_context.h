@@ -56,8 +56,9 @@ struct muca_context {
     int32_t* d_first = nullptr;
     int ntasks = 0, nblocks = 0;
     size_t need = 0;       // LDS bytes for the walker state of the largest set
-  } coop[5];  // lanes per walker / walkers per wavefront: [0] 16/4, [1] 64/1, [2] 16/2,
-              // [3] 16/1, [4] 64/1 with one set per block (LOOK4)
+  } coop[6];  // lanes per walker / walkers per wavefront: [0] 16/4, [1] 64/1, [2] 16/2,
+              // [3] 16/1, [4] 64/1 with one set per block (LOOK4), [5] 16/2 or 16/4
+              // per group (SUB16MIX)
   int num_cu = 256;        // compute units of the device
   size_t tbl_bytes = 0;    // largest threshold table of one group
   size_t hist_bytes = 0;   // largest histogram of one group

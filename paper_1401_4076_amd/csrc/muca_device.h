@@ -29,10 +29,11 @@ struct GroupDesc {
   int64_t pos_off;                // first particle entry of the group's walker 0
 };
 
-// A block of the cooperative sweep: walkers [first, first + count) (global
-// walker indices) of one group.
+// A set of walkers of the cooperative sweep: walkers [first, first + count)
+// (global walker indices) of one group, placed in every spread-th 16-lane row
+// of the block (spread 1 with 64 lanes per walker).
 struct SweepTask {
-  int32_t group, first, count, pad_;
+  int32_t group, first, count, spread;
 };
 
 // ---------------------------------------------------------------- Philox4x32-10

@@ -22,8 +22,7 @@ __global__ void k_sweep_sub(const GroupDesc* groups, const SweepTask* tasks, con
                             uint32_t* gbits, uint32_t* gpos, int32_t* gE, uint64_t* gT,
                             uint32_t* gtun, const uint32_t* thr, int32_t* H,
                             const int32_t* active, int sweeps,
-                            uint32_t first_id, uint32_t seed32, int tbl_words, int hist_words,
-                            int spread);
+                            uint32_t first_id, uint32_t seed32, int tbl_words, int hist_words);
 template <bool kTbl>
 __global__ void k_sweep_look(const GroupDesc* groups, const SweepTask* tasks, uint32_t* gbits,
                              uint32_t* gpos, int32_t* gE, uint64_t* gT, uint32_t* gtun,

@@ -142,19 +142,23 @@ int static_setup(int device) {
 
 // The plain task table of a cooperative layout: set i is walkers
 // [f, f + count) of one group, sets in group order, one set per block.
-__global__ void k_plain_tasks(const GroupDesc* __restrict__ groups, int ngroups, int wpb,
-                              SweepTask* __restrict__ tasks, int32_t* __restrict__ first,
-                              int nsets) {
+// spread > 0: every group's walkers in every spread-th row; spread = 0: two
+// walkers per wavefront for the groups with V = vmax, four for the others.
+__global__ void k_plain_tasks(const GroupDesc* __restrict__ groups, int ngroups, int lanes,
+                              int spread, int vmax, SweepTask* __restrict__ tasks,
+                              int32_t* __restrict__ first, int nsets) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) first[nsets] = nsets;
   if (i >= nsets) return;
   int base = 0;
   for (int gi = 0; gi < ngroups; ++gi) {
     const GroupDesc g = groups[gi];
+    const int sp = spread > 0 ? spread : (g.V == vmax ? 2 : 1);
+    const int wpb = 256 / lanes / sp;
     const int n = (g.walkers + wpb - 1) / wpb;
     if (i < base + n) {
       const int f = (i - base) * wpb;
-      tasks[i] = SweepTask{gi, g.first_walker + f, min(wpb, g.walkers - f), 0};
+      tasks[i] = SweepTask{gi, g.first_walker + f, min(wpb, g.walkers - f), sp};
       first[i] = i;
       return;
     }
@@ -199,9 +203,26 @@ int resolved_layout(muca_ctx c) {
 // with the long chains and stretch the launch (258 sets of 16 walkers on 256
 // CUs cost 30 % in the batched 2D workload).  Otherwise one set per block,
 // the groups interleaved so that every CU receives a mix of lattice sizes.
-constexpr int kCoopLanes[5] = {16, 64, 16, 16, 64};  // lanes per walker
-constexpr int kCoopSpread[5] = {1, 1, 2, 4, 1};      // 16-lane rows per walker row used
-constexpr bool kCoopPacked[5] = {true, true, true, true, false};
+constexpr int kCoops = 6;
+constexpr int kCoopLanes[kCoops] = {16, 64, 16, 16, 64, 16};  // lanes per walker
+// 16-lane rows per walker row used; 0: per group (SUB16MIX, see group_spread)
+constexpr int kCoopSpread[kCoops] = {1, 1, 2, 4, 1, 0};
+constexpr bool kCoopPacked[kCoops] = {true, true, true, true, false, true};
+
+// Rows per walker of group g in cooperative table `which`.  SUB16MIX: the
+// groups with the context's largest lattice get two walkers per wavefront
+// (their chains bound the launch, and fewer walkers per wavefront take the
+// rare paths less often), the others four.
+int group_spread(const muca_context* c, int which, const GroupDesc& g) {
+  if (kCoopSpread[which] > 0) return kCoopSpread[which];
+  int vmax = 0;
+  for (const auto& h : c->g) vmax = std::max(vmax, h.V);
+  return g.V == vmax ? 2 : 1;
+}
+
+int group_wpb(const muca_context* c, int which, const GroupDesc& g) {
+  return 256 / kCoopLanes[which] / group_spread(c, which, g);
+}
 
 // Task table (coop index) of a cooperative layout, -1 for the one-walker-per-
 // lane layout.
@@ -212,6 +233,7 @@ int coop_index(int layout) {
     case MUCA_LAYOUT_SUB16X2: return 2;
     case MUCA_LAYOUT_SUB16X1: return 3;
     case MUCA_LAYOUT_LOOK4: return 4;
+    case MUCA_LAYOUT_SUB16MIX: return 5;
     default: return -1;
   }
 }
@@ -220,11 +242,11 @@ int coop_index(int layout) {
 // the largest set (need), and the context's largest histogram and threshold
 // table of one group (hist_bytes, tbl_bytes).  No device work.
 size_t coop_sizes(muca_ctx c, int which) {
-  const int wpb = 256 / kCoopLanes[which] / kCoopSpread[which];
   size_t need = 0;
   c->hist_bytes = 0;
   c->tbl_bytes = 0;
   for (const auto& g : c->g) {
+    const int wpb = group_wpb(c, which, g);
     // per walker: (site, coordinates) pairs, bits rounded up to whole pairs;
     // one word of alignment slack before the first slot
     need = std::max(need, (size_t)wpb * (size_t)(2 * g.N + ((g.words + 1) & ~1)) *
@@ -238,14 +260,13 @@ size_t coop_sizes(muca_ctx c, int which) {
 int build_coop(muca_ctx c, int which) {
   auto& q = c->coop[which];
   if (q.d_tasks) return MUCA_OK;
-  const int G = kCoopLanes[which];
-  const int wpb = 256 / G / kCoopSpread[which];
   std::vector<std::vector<SweepTask>> per(c->ngroups);
   const size_t need = coop_sizes(c, which);
   for (int i = 0; i < c->ngroups; ++i) {
     const GroupDesc& g = c->g[i];
+    const int wpb = group_wpb(c, which, g), sp = group_spread(c, which, g);
     for (int f = 0; f < g.walkers; f += wpb)
-      per[i].push_back(SweepTask{i, g.first_walker + f, std::min(wpb, g.walkers - f), 0});
+      per[i].push_back(SweepTask{i, g.first_walker + f, std::min(wpb, g.walkers - f), sp});
   }
   std::vector<SweepTask> sets;
   for (size_t r = 0;; ++r) {
@@ -356,7 +377,7 @@ int launch_coop_tables(muca_ctx c, int which, const CoopTables& q, int sweeps, i
   hipLaunchKernelGGL(kern, dim3((unsigned)q.nblocks), dim3(256), dyn, s, c->d_groups, q.tasks,
                      q.first, c->d_bits, c->d_pos, c->d_E, c->d_T, c->d_tun, q.thr, H, active,
                      sweeps, c->first_id, c->seed32, tbl_words,
-                     state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0, kCoopSpread[which]);
+                     state_lds ? (int)(c->hist_bytes / sizeof(int32_t)) : 0);
   LAUNCH_CHECK();
   return MUCA_OK;
 }
@@ -422,6 +443,8 @@ int enqueue_sweep_kernel(muca_ctx c, int layout, int sweeps, int32_t* H, const i
       return launch_coop<16>(c, 2, sweeps, H, active, s);
     case MUCA_LAYOUT_SUB16X1:
       return launch_coop<16>(c, 3, sweeps, H, active, s);
+    case MUCA_LAYOUT_SUB16MIX:
+      return launch_coop<16>(c, 5, sweeps, H, active, s);
     default:
       return fail(MUCA_EINVAL, "unknown layout %d", layout);
   }
@@ -878,11 +901,13 @@ int mucaSweepNoAlloc(muca_ctx c, const double* lnW, int sweeps, int32_t* H, void
   const size_t thr_bytes = up((size_t)c->thr_entries * sizeof(uint32_t));
   const int which = coop_index(layout);  // -1: one walker per lane, no task table
   const int G = which >= 0 ? kCoopLanes[which] : 0;
-  int nsets = 0, wpb = 1;
-  if (which >= 0) {
-    wpb = 256 / kCoopLanes[which] / kCoopSpread[which];
-    for (const auto& g : c->g) nsets += (g.walkers + wpb - 1) / wpb;
-  }
+  int nsets = 0, vmax = 0;
+  if (which >= 0)
+    for (const auto& g : c->g) {
+      const int wpb = group_wpb(c, which, g);
+      nsets += (g.walkers + wpb - 1) / wpb;
+      vmax = std::max(vmax, g.V);
+    }
   const size_t task_bytes = which >= 0 ? up((size_t)nsets * sizeof(SweepTask)) : 0;
   const size_t first_bytes = which >= 0 ? up(((size_t)nsets + 1) * sizeof(int32_t)) : 0;
   if (thr_bytes + task_bytes + first_bytes > kStaticBytes)
@@ -905,7 +930,8 @@ int mucaSweepNoAlloc(muca_ctx c, const double* lnW, int sweeps, int32_t* H, void
     return MUCA_OK;
   }
   hipLaunchKernelGGL(k_plain_tasks, dim3((unsigned)((nsets + 255) / 256)), dim3(256), 0, s,
-                     c->d_groups, c->ngroups, wpb, tasks, first, nsets);
+                     c->d_groups, c->ngroups, kCoopLanes[which], kCoopSpread[which], vmax, tasks,
+                     first, nsets);
   LAUNCH_CHECK();
   const size_t need = coop_sizes(c, which);
   const CoopTables q{tasks, first, nsets, need, thr};
@@ -1010,7 +1036,7 @@ int mucaRun(muca_ctx c, double* lnW, double* P, int32_t* H, int sweeps_per_iter,
       c->graph_exec = nullptr;
       c->graph = nullptr;
       // task tables and kernel attributes are set up outside the capture
-      for (int which = 0; which < 5; ++which)
+      for (int which = 0; which < kCoops; ++which)
         if (int r = build_coop(c, which)) return r;
       HIP_TRY(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
       const int r = enqueue_iteration(rs);

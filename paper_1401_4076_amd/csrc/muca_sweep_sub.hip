@@ -28,8 +28,9 @@
 // recomputed in the batch phase.  kPipe (device memory only; the 16-lane
 // layouts): the gathers of the next kPipe attempts (1 or 2) are issued before
 // the current one is decided.
-// spread (16 lanes only): walkers sit in every spread-th 16-lane row, so a
-// small population fills more wavefronts (layouts SUB16X2, SUB16X1).
+// spread (16 lanes only, per task): walkers sit in every spread-th 16-lane
+// row, so a small population fills more wavefronts (layouts SUB16X2, SUB16X1,
+// and per group in SUB16MIX).
 #include "muca_kernels.h"
 
 #pragma clang fp contract(off)
@@ -470,8 +471,9 @@ __device__ __forceinline__ void run_set(
     uint32_t* __restrict__ gbits, uint32_t* __restrict__ gpos, int32_t* __restrict__ gE,
     uint64_t* __restrict__ gT, uint32_t* __restrict__ gtun, const uint32_t* __restrict__ thr,
     int32_t* __restrict__ H, const int32_t* __restrict__ active, int sweeps, uint32_t first_id,
-    uint32_t seed32, int tbl_words, int hist_words, int spread) {
+    uint32_t seed32, int tbl_words, int hist_words) {
   if (active && !active[task.group]) return;  // uniform per block
+  const int spread = task.spread;
   const GroupDesc g = groups[task.group];
   Walker<G, kLds, kTbl> W;
   W.g = &g;
@@ -659,7 +661,7 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
     uint32_t* __restrict__ gpos, int32_t* __restrict__ gE, uint64_t* __restrict__ gT,
     uint32_t* __restrict__ gtun, const uint32_t* __restrict__ thr, int32_t* __restrict__ H,
     const int32_t* __restrict__ active, int sweeps, uint32_t first_id, uint32_t seed32,
-    int tbl_words, int hist_words, int spread) {
+    int tbl_words, int hist_words) {
   static_assert(G == 16 || G == 64, "16 or 64 lanes per walker");
   static_assert(!(kLds && kPipe), "the pipelined gather is for device-memory state");
   static_assert(kPipe >= 0 && kPipe <= 2 && (G == 16 || kPipe == 0), "pipeline depth");
@@ -670,50 +672,49 @@ __global__ void __launch_bounds__(256) k_sweep_sub(
   for (int ti = t0; ti < t1; ++ti) {
     if (ti > t0) __syncthreads();  // the previous set is out of LDS
     run_set<G, kLds, kTbl, kPipe>(groups, tasks[ti], smem, gbits, gpos, gE, gT, gtun, thr, H,
-                                  active, sweeps, first_id, seed32, tbl_words, hist_words,
-                                  spread);
+                                  active, sweeps, first_id, seed32, tbl_words, hist_words);
   }
 }
 
 template __global__ void k_sweep_sub<16, true, true, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<16, true, false, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<16, false, true, 1>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<16, false, false, 1>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<16, false, true, 2>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<16, false, false, 2>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<64, true, true, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<64, true, false, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<64, false, true, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 template __global__ void k_sweep_sub<64, false, false, 0>(
     const GroupDesc*, const SweepTask*, const int32_t*, uint32_t*, uint32_t*, int32_t*,
     uint64_t*, uint32_t*, const uint32_t*, int32_t*, const int32_t*, int, uint32_t, uint32_t, int,
-    int, int);
+    int);
 
 }  // namespace muca

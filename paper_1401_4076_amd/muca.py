@@ -34,10 +34,11 @@ MUCA_LAYOUT_SUB64 = 3
 MUCA_LAYOUT_LOOK4 = 4
 MUCA_LAYOUT_SUB16X2 = 5
 MUCA_LAYOUT_SUB16X1 = 6
-MUCA_NUM_LAYOUTS = 7
+MUCA_LAYOUT_SUB16MIX = 7
+MUCA_NUM_LAYOUTS = 8
 MUCA_NOALLOC_WORKSPACE_BYTES = 4194304
 LAYOUTS = (MUCA_LAYOUT_LANE, MUCA_LAYOUT_SUB16, MUCA_LAYOUT_SUB64, MUCA_LAYOUT_LOOK4,
-           MUCA_LAYOUT_SUB16X2, MUCA_LAYOUT_SUB16X1)
+           MUCA_LAYOUT_SUB16X2, MUCA_LAYOUT_SUB16X1, MUCA_LAYOUT_SUB16MIX)
 
 # C ABI: name -> (restype, argtypes)
 _P = ctypes.POINTER

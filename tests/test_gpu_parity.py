@@ -168,9 +168,11 @@ VARIANTS = [(M.MUCA_LAYOUT_LANE, 163840), (M.MUCA_LAYOUT_SUB16, 163840),
             (M.MUCA_LAYOUT_SUB16, 0), (M.MUCA_LAYOUT_SUB64, 163840), (M.MUCA_LAYOUT_SUB64, 0),
             (M.MUCA_LAYOUT_SUB16, 24576), (M.MUCA_LAYOUT_LOOK4, 163840),
             (M.MUCA_LAYOUT_LOOK4, 24576), (M.MUCA_LAYOUT_SUB16X2, 163840),
-            (M.MUCA_LAYOUT_SUB16X2, 0), (M.MUCA_LAYOUT_SUB16X1, 163840)]
+            (M.MUCA_LAYOUT_SUB16X2, 0), (M.MUCA_LAYOUT_SUB16X1, 163840),
+            (M.MUCA_LAYOUT_SUB16MIX, 163840), (M.MUCA_LAYOUT_SUB16MIX, 0)]
 VARIANT_IDS = ["lane", "sub16-lds", "sub16-hbm", "sub64-lds", "sub64-hbm", "sub16-lds24k",
-               "look4", "look4-lds24k", "sub16x2-lds", "sub16x2-hbm", "sub16x1-lds"]
+               "look4", "look4-lds24k", "sub16x2-lds", "sub16x2-hbm", "sub16x1-lds",
+               "sub16mix-lds", "sub16mix-hbm"]
 
 
 def make_ctx(groups, seed, variant=None, first_id=0):
