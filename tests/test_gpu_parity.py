@@ -577,3 +577,43 @@ def test_run_resumed_in_chunks_equals_one_run():
     assert list(it) == list(rit) == list(it1) and list(fl) == list(rfl)
     assert np.array_equal(gH.cpu().numpy(), rH)
     assert same_f64(glnW.cpu().numpy(), lnW) and same_f64(gP.cpu().numpy(), P)
+
+
+@pytest.mark.parametrize("layout", [M.MUCA_LAYOUT_SUB16, M.MUCA_LAYOUT_SUB16X2])
+def test_resident_cap_rounds_match_oracle(layout):
+    """Walker state in device memory with more than two sets per CU: a
+    resident cap of one byte leaves one block per CU (the sets run in rounds,
+    two or more per block), no cap and the default cap two or more blocks per
+    CU; all equal the oracle."""
+    groups = [(2, 8, 16, 8300), (3, 8, 30, 300)]  # 538 sets of 16 (SUB16)
+    ref = O.RefContext(groups, seed=12)
+    lnW = W.random_lnW(ref.total_bins, seed=13, scale=0.8)
+    rH = ref.sweep(lnW, 4)
+    for cap in (1, 0, 234881024):
+        say("resident cap", cap, "layout", layout)
+        ctx = make_ctx(groups, 12, (layout, 0))
+        ctx.set_resident_limit(cap)
+        assert ctx.resident_limit() == cap
+        assert ctx.placement() == (False, False)
+        H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=DEV)
+        ctx.sweep(dev_f64(lnW), 4, H)
+        torch.cuda.synchronize()
+        assert np.array_equal(H.cpu().numpy(), rH), cap
+        assert_walkers_equal(ctx, ref, list(range(0, ctx.nwalkers, 97)) + [ctx.nwalkers - 1])
+        ctx.close()
+
+
+def test_placement_reports_where_state_lives():
+    ctx = M.Context([(2, 8, 16, 40)], seed=1)
+    ctx.set_layout(M.MUCA_LAYOUT_SUB16)
+    assert ctx.placement() == (True, True)
+    ctx.set_lds_limit(0)
+    assert ctx.placement() == (False, False)
+    ctx.set_layout(M.MUCA_LAYOUT_LANE)
+    assert ctx.placement() == (False, False)
+    ctx.close()
+    big = M.Context([(3, 48, 3318, 16)], seed=1)  # bricked: device memory in every layout
+    for lay in (M.MUCA_LAYOUT_SUB16, M.MUCA_LAYOUT_SUB16X2, M.MUCA_LAYOUT_SUB64):
+        big.set_layout(lay)
+        assert big.placement() == (False, False)
+    big.close()
