@@ -73,9 +73,9 @@ def main():
         net.set_params(np.load(args.net).astype(np.float32))
     else:
         net = train_stage(args, out)
-        if args.net:
+        if net is not None and args.net:
             np.save(args.net, net.get_params())
-    if args.stage != "train":
+    if args.stage != "train" and net is not None:
         eval_stage(args, net, out)
     print(json.dumps(out), flush=True)
 
@@ -120,6 +120,10 @@ def train_stage(args, out):
             Xs.append(X)
             Ts.append(T)
         run["ctx"].close()
+    if not Xs:
+        out["train_rows"] = 0
+        log("no training table converged: nothing to train")
+        return None
     X, T = torch.cat(Xs), torch.cat(Ts)
     out["train_rows"] = int(X.shape[0])
     net = M.Mlp(max(X.shape[0], 16384))
