@@ -216,6 +216,31 @@ def calibrate_copy(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
+def calibrate_random_lines(table_bytes, reads=1 << 25, reps=5):
+    """Random-access rate of the device: gathers of `reads` uniformly random
+    128-byte rows from a table of table_bytes (index_select; its output is
+    written sequentially).  Prints the read rate of whole lines in GB/s."""
+    import torch
+    rows = table_bytes // 128
+    table = torch.ones((rows, 32), dtype=torch.int32, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    idx = torch.randint(0, rows, (reads,), device="cuda", generator=g)
+    out = torch.empty((reads, 32), dtype=torch.int32, device="cuda")
+    torch.index_select(table, 0, idx, out=out)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.index_select(table, 0, idx, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    print(json.dumps({"table_bytes": rows * 128, "random_128B_reads": reads,
+                      "read_GBps": reads * 128 / sec / 1e9,
+                      "read_and_write_GBps": reads * 256 / sec / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +258,8 @@ def main():
                          "device memory (MiB, 0 = none; default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--calibrate-random-lines", type=int, default=0, metavar="TABLE_BYTES",
+                    help="time random 128-byte row gathers from a table of this size")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -241,6 +268,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.calibrate_random_lines:
+        calibrate_random_lines(args.calibrate_random_lines)
         return
 
     import torch
