@@ -35,6 +35,10 @@ import workloads as W  # noqa: E402
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
 LDS_PEAK = 256 * 128 * 2.4e9
+# Measured rate of random whole 128-byte line reads from HBM on MI355X
+# (bench.py --calibrate-random-lines 4294967296): the ceiling of the sweeps
+# whose walker state lives in device memory.
+RANDOM_LINE_PEAK = 6.58e12
 
 # One Philox4x32-10 block: 10 rounds of two 32x32->64 products (quarter rate:
 # 4 full-rate lane-op equivalents each), two three-input XORs and the key
@@ -216,29 +220,18 @@ def calibrate_copy(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
-def calibrate_random_lines(table_bytes, reads=1 << 25, reps=5):
-    """Random-access rate of the device: gathers of `reads` uniformly random
-    128-byte rows from a table of table_bytes (index_select; its output is
-    written sequentially).  Prints the read rate of whole lines in GB/s."""
+def calibrate_random_lines(table_bytes, rounds=256):
+    """The device's rate of random whole-line reads (mucaCalibrateRandomLines):
+    8 independent random 128-byte lines per lane and round, 2048 blocks of
+    256 lanes.  Prints lines/s and the bytes of those lines per second."""
     import torch
-    rows = table_bytes // 128
-    table = torch.ones((rows, 32), dtype=torch.int32, device="cuda")
-    g = torch.Generator(device="cuda")
-    g.manual_seed(1)
-    idx = torch.randint(0, rows, (reads,), device="cuda", generator=g)
-    out = torch.empty((reads, 32), dtype=torch.int32, device="cuda")
-    torch.index_select(table, 0, idx, out=out)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        torch.index_select(table, 0, idx, out=out)
-    b.record()
-    torch.cuda.synchronize()
-    sec = a.elapsed_time(b) * 1e-3 / reps
-    print(json.dumps({"table_bytes": rows * 128, "random_128B_reads": reads,
-                      "read_GBps": reads * 128 / sec / 1e9,
-                      "read_and_write_GBps": reads * 256 / sec / 1e9}), flush=True)
+    from paper_1401_4076_amd import muca as M
+    table = torch.ones(table_bytes // 4, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(2048 * 256, dtype=torch.int32, device="cuda")
+    lines, sec = M.calibrate_random_lines(table, sink, rounds)
+    print(json.dumps({"table_bytes": table_bytes, "lines": lines, "seconds": sec,
+                      "lines_per_s": lines / sec, "line_GBps": lines * 128 / sec / 1e9}),
+          flush=True)
 
 
 def main():
@@ -353,6 +346,11 @@ def main():
                 "unit": "GB/s", "frac": hbm["frac"], "traffic": traffic}
     roof.update({"valu": valu, "hbm": hbm, "lds": lds,
                  "traffic_per_attempt": None if traffic is None else traffic / per_step})
+    if traffic is not None and not state_lds:
+        moved = traffic / (sweep_ms * 1e-3)  # counter bytes per second of the launch
+        roof["moved"] = {"achieved": moved, "unit": "B/s",
+                         "random_line_peak": RANDOM_LINE_PEAK,
+                         "frac_of_random_line_peak": moved / RANDOM_LINE_PEAK}
     out = {
         "metric": "move attempts/s on 1 GPU",
         "value": value,

@@ -338,6 +338,20 @@ int mucaReweightObservable(muca_ctx ctx, const double* lnW, const int32_t* ocoun
                            const long long* osum, const double* beta, int nbeta, double* out,
                            void* stream);
 
+/* Calibration of the memory-bound roofline of the sweeps with walker state in
+ * device memory, whose attempts read a few random 128-byte lines each: the
+ * device's rate of random whole-line reads.  sink_words / 256 blocks of 256
+ * lanes (at most 2^20 blocks) each follow 8 independent xorshift32 streams
+ * of uniformly random lines of `table` (device, table_bytes bytes, at least
+ * one 128-byte line, at most 2^32 - 1) for `rounds` rounds, one 4-byte load
+ * per line, and store one word per lane into sink (device).  One untimed
+ * launch, then a timed one (HIP events on stream); lines_read and seconds
+ * (host) describe the timed launch.  Synchronous.  A table larger than the
+ * last-level cache measures HBM, a smaller one the caches. */
+int mucaCalibrateRandomLines(const uint32_t* table, int64_t table_bytes, uint32_t* sink,
+                             int64_t sink_words, int rounds, double* lines_read, double* seconds,
+                             void* stream);
+
 /* enable = 0 makes mucaRun enqueue every iteration eagerly on the caller's
  * stream instead of replaying the captured graph (same results). */
 int mucaSetGraph(muca_ctx ctx, int enable);

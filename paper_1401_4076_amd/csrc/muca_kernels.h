@@ -43,6 +43,8 @@ __global__ void k_largest_cluster(const GroupDesc* groups, const int32_t* wgroup
 __global__ void k_reweight_obs(const GroupDesc* groups, const double* lnW, const int32_t* cnt,
                                const long long* osum, const double* beta, int nbeta,
                                double* out);
+__global__ void k_random_lines(const uint32_t* table, uint32_t lines, int rounds, uint32_t seed,
+                               uint32_t* sink);
 __global__ void k_bump(int32_t* counter);
 __global__ void k_fill_i32(int32_t* p, int32_t v, int n);
 __global__ void k_fill_f64(double* p, double v, int n);

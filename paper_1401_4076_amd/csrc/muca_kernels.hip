@@ -568,6 +568,36 @@ __global__ void __launch_bounds__(256) k_reweight_obs(const GroupDesc* __restric
   if (threadIdx.x == 0) out[(size_t)gi * nbeta + k] = so / z;
 }
 
+// ---------------------------------------------------------------- calibration
+// Random-line read rate of the device: every lane follows 8 independent
+// streams of uniformly random 128-byte lines of the table (one 4-byte load
+// per line, so each miss moves a whole line) and folds the values into one
+// word per lane.  Streams are xorshift32 generators; a line index is
+// floor(x lines / 2^32).
+__global__ void __launch_bounds__(256) k_random_lines(const uint32_t* __restrict__ table,
+                                                      uint32_t lines, int rounds, uint32_t seed,
+                                                      uint32_t* __restrict__ sink) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = (tid * 8u + (uint32_t)j) * 0x9E3779B9u + seed + 1u;
+  uint32_t acc = 0u;
+  for (int r = 0; r < rounds; ++r) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      x[j] ^= x[j] << 13;
+      x[j] ^= x[j] >> 17;
+      x[j] ^= x[j] << 5;
+      const uint32_t line = __umulhi(x[j], lines);
+      v[j] = table[(size_t)line * 32u];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  sink[tid] = acc;
+}
+
 __global__ void k_bump(int32_t* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter += 1;
 }

@@ -79,6 +79,9 @@ SIGNATURES = {
                                       _P(ctypes.c_uint32), _P(_i32), _P(ctypes.c_uint64)]),
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
     "mucaSetTunnelTarget": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mucaCalibrateRandomLines": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, ctypes.c_int64,
+                                                ctypes.c_int, _P(ctypes.c_double),
+                                                _P(ctypes.c_double), _vp]),
     "mucaReweight": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "mucaLargestCluster": (ctypes.c_int, [_vp, _vp, _vp]),
     "mucaMeasureDroplets": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -346,6 +349,18 @@ class Context:
         t = ctypes.c_uint64()
         _check(lib().mucaReadWalker(self._h, int(w), bits, pos, ctypes.byref(E), ctypes.byref(t)))
         return list(bits), list(pos), E.value, t.value
+
+
+def calibrate_random_lines(table, sink, rounds, stream=None):
+    """mucaCalibrateRandomLines on a device uint8/int32 table and int32 sink;
+    returns (lines read, seconds) of the timed launch."""
+    lines, sec = ctypes.c_double(), ctypes.c_double()
+    nbytes = table.numel() * table.element_size()
+    _check(lib().mucaCalibrateRandomLines(ctypes.c_void_p(table.data_ptr()), int(nbytes),
+                                          ctypes.c_void_p(sink.data_ptr()), int(sink.numel()),
+                                          int(rounds), ctypes.byref(lines), ctypes.byref(sec),
+                                          _stream(stream)))
+    return lines.value, sec.value
 
 
 def mucaDefaultWindow(d, L, N):

@@ -617,3 +617,17 @@ def test_placement_reports_where_state_lives():
         big.set_layout(lay)
         assert big.placement() == (False, False)
     big.close()
+
+
+def test_random_line_calibration_reads_every_line_it_counts():
+    """mucaCalibrateRandomLines on a table of ones: every lane folds 8 loads
+    per round, so each sink word is 8 x rounds; bad arguments are refused."""
+    table = torch.ones((1 << 20) // 4, dtype=torch.int32, device=DEV)  # 8192 lines
+    sink = torch.zeros(512 * 256, dtype=torch.int32, device=DEV)
+    lines, sec = M.calibrate_random_lines(table, sink, 5)
+    assert lines == 512 * 256 * 8 * 5 and sec > 0
+    assert int((sink != 40).sum().item()) == 0
+    with pytest.raises(M.MucaError):
+        M.calibrate_random_lines(table[:8], sink, 5)  # less than one 128-byte line
+    with pytest.raises(M.MucaError):
+        M.calibrate_random_lines(table, sink[:100], 5)
