@@ -363,6 +363,28 @@ int mucaSetGraph(muca_ctx ctx, int enable);
 int mucaReadWalker(muca_ctx ctx, int walker, uint32_t* bits, uint32_t* pos, int32_t* E,
                    uint64_t* t);
 
+/* Checkpoint and resume (not part of the paper's method; lets one run of
+ * the iteration of Sec. 2 span several processes or sessions).
+ * mucaStateBytes: size in bytes of the context's state image.
+ * mucaSaveState: waits for the device and writes the image into the host
+ *   buffer image (bytes >= mucaStateBytes, else MUCA_EINVAL): a header, the
+ *   group list, every walker's occupation bits (in the context's own bit
+ *   layout), particle sites, energy, attempt counter and tunnelling state,
+ *   and the loop state of mucaRun (finished groups, iteration counts) and
+ *   the tunnelling target.  The caller-owned lnW, P and H are not in it:
+ *   the caller keeps copies taken at the same point.
+ * mucaLoadState: overwrites the context's state with an image saved from a
+ *   context created with the same groups, seed and first walker id (else
+ *   MUCA_EINVAL, as for a truncated image, another format or a checksum
+ *   mismatch; the context is then unchanged); waits for the device.
+ *   Afterwards mucaSweep and mucaRun(resume = 1) with the saved lnW and P
+ *   continue bit-identically to the run the image was saved from, since
+ *   the random streams are counter-based.
+ * The image is host-endian and meant for the same library build. */
+int mucaStateBytes(muca_ctx ctx, int64_t* bytes);
+int mucaSaveState(muca_ctx ctx, void* image, int64_t bytes);
+int mucaLoadState(muca_ctx ctx, const void* image, int64_t bytes);
+
 /* Synchronise the context's last stream and report a pending device-side
  * error (MUCA_ENONFINITE) or MUCA_OK.  Clears the pending error. */
 int mucaStatus(muca_ctx ctx, void* stream);

@@ -1146,6 +1146,61 @@ int droplet_attr(size_t need) {
   return MUCA_OK;
 }
 
+// ---------------------------------------------------------------- checkpoint
+// State image of mucaSaveState / mucaLoadState: a header, one muca_group
+// record per group (window resolved), then the device arrays below, in this
+// order.  It holds everything that later iterations read from library
+// memory: the walker state (whose random streams are counter-based, so the
+// attempt counters resume them exactly) and the loop state of mucaRun.
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, ngroups, seed32, first_id;
+  int32_t nwalkers, tunnel_target, run_started, reserved;
+  int64_t total_words, total_pos;
+  uint64_t payload_bytes;  // bytes after the header
+  uint64_t checksum;       // FNV-1a (64 bit) of those bytes
+};
+constexpr char kCkptMagic[8] = {'M', 'U', 'C', 'A', 'S', 'T', 'A', 'T'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptSection {
+  void* dev;
+  size_t bytes;
+};
+
+std::vector<CkptSection> ckpt_sections(muca_ctx c) {
+  const size_t W = (size_t)c->nwalkers, G = (size_t)c->ngroups;
+  return {{c->d_bits, sizeof(uint32_t) * (size_t)c->total_words},
+          {c->d_pos, sizeof(uint32_t) * (size_t)c->total_pos},
+          {c->d_E, sizeof(int32_t) * W},
+          {c->d_T, sizeof(uint64_t) * W},
+          {c->d_tun, sizeof(uint32_t) * W},
+          {c->d_active, sizeof(int32_t) * G},
+          {c->d_flat, sizeof(int32_t) * G},
+          {c->d_iters, sizeof(int32_t) * G},
+          {c->d_counter, sizeof(int32_t) * 2}};
+}
+
+size_t ckpt_payload(muca_ctx c) {
+  size_t n = sizeof(muca_group) * (size_t)c->ngroups;
+  for (const auto& q : ckpt_sections(c)) n += q.bytes;
+  return n;
+}
+
+muca_group ckpt_group(const GroupDesc& g) {
+  return muca_group{g.d, g.L, g.N, g.walkers, g.e_lo, g.e_hi};
+}
+
+// Fowler-Noll-Vo FNV-1a, 64-bit offset basis and prime.
+uint64_t fnv1a64(const unsigned char* p, size_t n) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1272,6 +1327,91 @@ int mucaGetTunnel(muca_ctx c, uint32_t* last_end, uint32_t* trips) {
     if (last_end) last_end[i] = st[i] & 3u;
     if (trips) trips[i] = st[i] >> 2;
   }
+  return MUCA_OK;
+}
+
+int mucaStateBytes(muca_ctx c, int64_t* bytes) {
+  if (int r = check_ctx(c)) return r;
+  if (!bytes) return fail(MUCA_EINVAL, "bytes must not be NULL");
+  *bytes = (int64_t)(sizeof(CkptHeader) + ckpt_payload(c));
+  return MUCA_OK;
+}
+
+int mucaSaveState(muca_ctx c, void* image, int64_t bytes) {
+  if (int r = check_ctx(c)) return r;
+  const size_t payload = ckpt_payload(c), need = sizeof(CkptHeader) + payload;
+  if (!image) return fail(MUCA_EINVAL, "image must not be NULL");
+  if (bytes < (int64_t)need)
+    return fail(MUCA_EINVAL, "state image needs %zu bytes, got %lld", need, (long long)bytes);
+  HIP_TRY(hipDeviceSynchronize());
+  unsigned char* out = static_cast<unsigned char*>(image);
+  unsigned char* p = out + sizeof(CkptHeader);
+  for (const auto& g : c->g) {
+    const muca_group r = ckpt_group(g);
+    std::memcpy(p, &r, sizeof r);
+    p += sizeof r;
+  }
+  for (const auto& q : ckpt_sections(c)) {
+    HIP_TRY(hipMemcpy(p, q.dev, q.bytes, hipMemcpyDeviceToHost));
+    p += q.bytes;
+  }
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, sizeof h.magic);
+  h.version = kCkptVersion;
+  h.ngroups = (uint32_t)c->ngroups;
+  h.seed32 = c->seed32;
+  h.first_id = c->first_id;
+  h.nwalkers = c->nwalkers;
+  h.tunnel_target = c->tunnel_target;
+  h.run_started = c->run_started ? 1 : 0;
+  h.total_words = c->total_words;
+  h.total_pos = c->total_pos;
+  h.payload_bytes = payload;
+  h.checksum = fnv1a64(out + sizeof(CkptHeader), payload);
+  std::memcpy(out, &h, sizeof h);
+  return MUCA_OK;
+}
+
+int mucaLoadState(muca_ctx c, const void* image, int64_t bytes) {
+  if (int r = check_ctx(c)) return r;
+  if (!image) return fail(MUCA_EINVAL, "image must not be NULL");
+  const size_t payload = ckpt_payload(c), need = sizeof(CkptHeader) + payload;
+  if (bytes < (int64_t)sizeof(CkptHeader))
+    return fail(MUCA_EINVAL, "state image of %lld bytes has no header", (long long)bytes);
+  const unsigned char* in = static_cast<const unsigned char*>(image);
+  CkptHeader h;
+  std::memcpy(&h, in, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, sizeof h.magic) != 0 || h.version != kCkptVersion)
+    return fail(MUCA_EINVAL, "not a state image of this library (magic or version)");
+  if (h.ngroups != (uint32_t)c->ngroups || h.nwalkers != c->nwalkers ||
+      h.total_words != c->total_words || h.total_pos != c->total_pos ||
+      h.payload_bytes != payload)
+    return fail(MUCA_EINVAL, "state image was saved from a context of other groups");
+  if (bytes < (int64_t)need)
+    return fail(MUCA_EINVAL, "state image truncated: %lld of %zu bytes", (long long)bytes, need);
+  if (h.seed32 != c->seed32 || h.first_id != c->first_id)
+    return fail(MUCA_EINVAL, "state image was saved with seed %u, first id %u (context: %u, %u)",
+                h.seed32, h.first_id, c->seed32, c->first_id);
+  if (h.tunnel_target < 1 || (h.run_started != 0 && h.run_started != 1))
+    return fail(MUCA_EINVAL, "state image header is corrupt");
+  const unsigned char* p = in + sizeof(CkptHeader);
+  if (fnv1a64(p, payload) != h.checksum)
+    return fail(MUCA_EINVAL, "state image checksum mismatch (corrupt image)");
+  for (const auto& g : c->g) {
+    muca_group r;
+    std::memcpy(&r, p, sizeof r);
+    const muca_group m = ckpt_group(g);
+    if (std::memcmp(&r, &m, sizeof r) != 0)
+      return fail(MUCA_EINVAL, "state image was saved from a context of other groups");
+    p += sizeof r;
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  for (const auto& q : ckpt_sections(c)) {
+    HIP_TRY(hipMemcpy(q.dev, p, q.bytes, hipMemcpyHostToDevice));
+    p += q.bytes;
+  }
+  c->tunnel_target = h.tunnel_target;
+  c->run_started = h.run_started != 0;
   return MUCA_OK;
 }
 

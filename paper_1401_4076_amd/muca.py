@@ -78,6 +78,9 @@ SIGNATURES = {
     "mucaReadWalker": (ctypes.c_int, [_vp, ctypes.c_int, _P(ctypes.c_uint32),
                                       _P(ctypes.c_uint32), _P(_i32), _P(ctypes.c_uint64)]),
     "mucaStatus": (ctypes.c_int, [_vp, _vp]),
+    "mucaStateBytes": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+    "mucaSaveState": (ctypes.c_int, [_vp, _vp, ctypes.c_int64]),
+    "mucaLoadState": (ctypes.c_int, [_vp, _vp, ctypes.c_int64]),
     "mucaSetTunnelTarget": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mucaCalibrateRandomLines": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, ctypes.c_int64,
                                                 ctypes.c_int, _P(ctypes.c_double),
@@ -334,6 +337,23 @@ class Context:
     def status(self, stream=None):
         return _check(lib().mucaStatus(self._h, _stream(stream)))
 
+    def state_bytes(self):
+        n = ctypes.c_int64()
+        _check(lib().mucaStateBytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def save_state(self):
+        """mucaSaveState into a new host bytearray (the state image)."""
+        n = self.state_bytes()
+        buf = bytearray(n)
+        _check(lib().mucaSaveState(self._h, (ctypes.c_char * n).from_buffer(buf), n))
+        return buf
+
+    def load_state(self, image):
+        """mucaLoadState from a bytes-like state image."""
+        data = bytes(image)
+        _check(lib().mucaLoadState(self._h, data, len(data)))
+
     def read_walker(self, w):
         """(bits[words] uint32 list, pos[N] list, E, t) of walker w."""
         acc = 0
@@ -408,6 +428,14 @@ def mucaRun(ctx, lnW, P, H, sweeps_per_iter, max_iters, rule=MUCA_RULE_BERG, sto
 
 def mucaReadWalker(ctx, walker):
     return ctx.read_walker(walker)
+
+
+def mucaSaveState(ctx):
+    return ctx.save_state()
+
+
+def mucaLoadState(ctx, image):
+    return ctx.load_state(image)
 
 
 def mucaDestroy(ctx):

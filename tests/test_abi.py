@@ -74,6 +74,10 @@ def test_null_arguments_rejected():
     assert L.mucaUpdateWeights(None, None, None, None, 0, None) == M.MUCA_EINVAL
     assert L.mucaDestroy(None) == M.MUCA_OK
     assert L.mucaDefaultWindow(2, 8, 4, None, None) == M.MUCA_EINVAL
+    nb = ctypes.c_int64()
+    assert L.mucaStateBytes(None, ctypes.byref(nb)) == M.MUCA_EINVAL
+    assert L.mucaSaveState(None, None, 0) == M.MUCA_EINVAL
+    assert L.mucaLoadState(None, b"MUCASTAT", 8) == M.MUCA_EINVAL
 
 
 @pytest.mark.parametrize("d,L,Ns", [
