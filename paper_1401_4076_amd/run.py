@@ -10,6 +10,9 @@ visited part of its window (lowest and highest visited energy, fraction of
 the bins) and min/max of H over the visited bins; for the whole iteration
 its wall time, the move attempts it made and their rate.
 
+--net starts from the learned network's proposal (its inference time is
+reported apart) instead of flat weights.
+
 A checkpoint file (.npz: the library's state image from mucaSaveState, the
 caller-owned lnW, P and H, and the run's parameters as JSON) is written
 every --checkpoint-every iterations and at the end; --resume continues from
@@ -122,6 +125,9 @@ def build_parser():
     ap.add_argument("--checkpoint-every", type=int, default=0,
                     help="also write the checkpoint every K iterations")
     ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
+    ap.add_argument("--net", default=None,
+                    help="start from the learned network's proposal (float32 parameter .npy) "
+                         "instead of flat weights")
     return ap
 
 
@@ -135,7 +141,8 @@ def run_config(args):
             "groups": [list(g) for g in groups],
             "seed": int(wl["seed"] if args.seed is None else args.seed),
             "sweeps": int(wl["sweeps"]), "rule": args.rule, "stop": args.stop,
-            "tunnel_target": int(args.tunnel_target)}
+            "tunnel_target": int(args.tunnel_target),
+            "init": "flat" if not args.net else "learned:" + os.path.basename(args.net)}
 
 
 def main(argv=None):
@@ -157,6 +164,7 @@ def main(argv=None):
     ctx.set_tunnel_target(cfg["tunnel_target"])
     dev = torch.device("cuda")
     done, iters_before, all_stopped, flat = 0, [0] * ctx.ngroups, False, [0] * ctx.ngroups
+    inference = 0.0
     if args.resume:
         image, lnW_h, P_h, H_h, saved = load_checkpoint(args.checkpoint)
         check_meta(saved, cfg)
@@ -167,6 +175,17 @@ def main(argv=None):
         done, iters_before = saved["iterations"], list(saved["iters"])
         all_stopped, flat = bool(saved["stopped"]), list(saved["flat"])
         log(f"resumed {args.checkpoint} after {done} iterations")
+    elif args.net:
+        from paper_1401_4076_amd import learned as LR
+        t0 = time.perf_counter()
+        net = M.Mlp(16384)
+        net.set_params(np.load(args.net, allow_pickle=False).astype(np.float32))
+        lnW = LR.predict(net, ctx)  # synchronised
+        net.close()
+        inference = time.perf_counter() - t0
+        log(f"initial weights from {args.net}: {inference:.3f} s")
+        P = torch.zeros_like(lnW)
+        H = torch.zeros(ctx.total_bins, dtype=torch.int32, device=dev)
     else:
         lnW = torch.zeros(ctx.total_bins, dtype=torch.float64, device=dev)
         P = torch.zeros_like(lnW)
@@ -220,7 +239,8 @@ def main(argv=None):
         logf.close()
     out = dict(cfg, iterations=done, iters=[int(x) for x in iters_before],
                flat=[int(x) for x in flat], stopped=all_stopped,
-               seconds=round(time.perf_counter() - t_start, 3), checkpoint=args.checkpoint)
+               seconds=round(time.perf_counter() - t_start, 3), checkpoint=args.checkpoint,
+               inference_seconds=round(inference, 3))
     print(json.dumps(out), flush=True)
     out["lnW"], out["P"], out["H"] = lnW.cpu().numpy(), P.cpu().numpy(), H.cpu().numpy()
     ctx.close()
