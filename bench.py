@@ -371,6 +371,7 @@ def main():
                    "resident_limit_bytes": ctx.resident_limit(),
                    "autotune_probe_ms": tune_ms},
         "sweep_kernel_ms": sweep_ms,
+        "sweep_attempts_per_s": kernel_rate,  # attempts / sweep-phase time (value: whole steps)
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
