@@ -100,6 +100,64 @@ def measured_traffic(workload, kernel_layout, attempts):
     return rec["bytes_per_attempt"] * attempts
 
 
+def bench_record(workload, groups, sweeps, steps, warmup, seconds, sweep_ms, layout, state_lds,
+                 table_lds, resident_limit, tune_ms, traffic):
+    """The JSON record of a timed run (host arithmetic only): `steps`
+    iterations took `seconds` in all and the sweep launch `sweep_ms` on
+    average; traffic = counter bytes per launch or None."""
+    per_step = attempts_per_sweep(groups) * sweeps
+    value = per_step * steps / seconds
+    kernel_rate = per_step / (sweep_ms * 1e-3)  # attempts/s inside the sweep launch
+    ops = _weighted(groups, valu_ops_per_attempt)
+    sbytes = _weighted(groups, state_bytes_per_attempt)
+    valu = {"achieved": ops * kernel_rate, "peak": VALU_PEAK_OPS, "unit": "int32 lane-op/s",
+            "frac": ops * kernel_rate / VALU_PEAK_OPS, "per_attempt": ops}
+    # the walker state is read from device memory or from LDS, not both
+    state_rate = sbytes * kernel_rate
+    hbm = {"achieved": 0.0 if state_lds else state_rate, "peak": HBM_PEAK, "unit": "B/s",
+           "per_attempt": 0.0 if state_lds else sbytes}
+    hbm["frac"] = hbm["achieved"] / HBM_PEAK
+    lds = {"achieved": state_rate if state_lds else 0.0, "peak": LDS_PEAK, "unit": "B/s",
+           "per_attempt": sbytes if state_lds else 0.0}
+    lds["frac"] = lds["achieved"] / LDS_PEAK
+    if state_lds:
+        roof = {"bound": "alu", "achieved": valu["achieved"], "peak": VALU_PEAK_OPS,
+                "unit": "int32 lane-op/s", "frac": valu["frac"], "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm["achieved"] / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": hbm["frac"], "traffic": traffic}
+    roof.update({"valu": valu, "hbm": hbm, "lds": lds,
+                 "traffic_per_attempt": None if traffic is None else traffic / per_step})
+    if traffic is not None and not state_lds:
+        moved = traffic / (sweep_ms * 1e-3)  # counter bytes per second of the launch
+        roof["moved"] = {"achieved": moved, "unit": "B/s",
+                         "random_line_peak": RANDOM_LINE_PEAK,
+                         "frac_of_random_line_peak": moved / RANDOM_LINE_PEAK}
+    return {
+        "metric": "move attempts/s on 1 GPU",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": seconds * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": workload, "groups": [list(g) for g in groups],
+                   "walkers": sum(g[3] for g in groups), "sweeps_per_iter": sweeps,
+                   "attempts_per_step": per_step, "rule": "berg", "layout": layout,
+                   "state_in_lds": state_lds, "table_in_lds": table_lds,
+                   "resident_limit_bytes": resident_limit,
+                   "autotune_probe_ms": tune_ms},
+        "sweep_kernel_ms": sweep_ms,
+        "sweep_attempts_per_s": kernel_rate,  # attempts / sweep-phase time (value: whole steps)
+        "roofline": roof,
+    }
+
+
 def cpu_threads():
     """Host cores for the oracle: the process's CPU set, at most 16 (one
     GPU's share of the host)."""
@@ -320,60 +378,10 @@ def main():
     t1 = time.perf_counter()
     ctx.status(stream)
 
-    per_step = attempts_per_sweep(groups) * sweeps
-    dt = t1 - t0
-    value = per_step * args.steps / dt
     sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    kernel_rate = per_step / (sweep_ms * 1e-3)  # attempts/s inside the sweep launch
-    ops = _weighted(groups, valu_ops_per_attempt)
-    sbytes = _weighted(groups, state_bytes_per_attempt)
-    valu = {"achieved": ops * kernel_rate, "peak": VALU_PEAK_OPS, "unit": "int32 lane-op/s",
-            "frac": ops * kernel_rate / VALU_PEAK_OPS, "per_attempt": ops}
-    # the walker state is read from device memory or from LDS, not both
-    state_rate = sbytes * kernel_rate
-    hbm = {"achieved": 0.0 if state_lds else state_rate, "peak": HBM_PEAK, "unit": "B/s",
-           "per_attempt": 0.0 if state_lds else sbytes}
-    hbm["frac"] = hbm["achieved"] / HBM_PEAK
-    lds = {"achieved": state_rate if state_lds else 0.0, "peak": LDS_PEAK, "unit": "B/s",
-           "per_attempt": sbytes if state_lds else 0.0}
-    lds["frac"] = lds["achieved"] / LDS_PEAK
-    traffic = measured_traffic(args.workload, ctx.layout(), per_step)
-    if state_lds:
-        roof = {"bound": "alu", "achieved": valu["achieved"], "peak": VALU_PEAK_OPS,
-                "unit": "int32 lane-op/s", "frac": valu["frac"], "traffic": traffic}
-    else:
-        roof = {"bound": "hbm", "achieved": hbm["achieved"] / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": hbm["frac"], "traffic": traffic}
-    roof.update({"valu": valu, "hbm": hbm, "lds": lds,
-                 "traffic_per_attempt": None if traffic is None else traffic / per_step})
-    if traffic is not None and not state_lds:
-        moved = traffic / (sweep_ms * 1e-3)  # counter bytes per second of the launch
-        roof["moved"] = {"achieved": moved, "unit": "B/s",
-                         "random_line_peak": RANDOM_LINE_PEAK,
-                         "frac_of_random_line_peak": moved / RANDOM_LINE_PEAK}
-    out = {
-        "metric": "move attempts/s on 1 GPU",
-        "value": value,
-        "unit": "attempts/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "groups": [list(g) for g in groups],
-                   "walkers": sum(g[3] for g in groups), "sweeps_per_iter": sweeps,
-                   "attempts_per_step": per_step, "rule": "berg", "layout": ctx.layout(),
-                   "state_in_lds": state_lds, "table_in_lds": table_lds,
-                   "resident_limit_bytes": ctx.resident_limit(),
-                   "autotune_probe_ms": tune_ms},
-        "sweep_kernel_ms": sweep_ms,
-        "sweep_attempts_per_s": kernel_rate,  # attempts / sweep-phase time (value: whole steps)
-        "roofline": roof,
-    }
+    traffic = measured_traffic(args.workload, ctx.layout(), attempts_per_sweep(groups) * sweeps)
+    out = bench_record(args.workload, groups, sweeps, args.steps, args.warmup, t1 - t0, sweep_ms,
+                       ctx.layout(), state_lds, table_lds, ctx.resident_limit(), tune_ms, traffic)
     if not args.no_cpu_baseline:
         nt = cpu_threads()
         print(f"bench: CPU oracle sample on 1 and {nt} threads", file=sys.stderr, flush=True)

@@ -82,3 +82,40 @@ def test_per_attempt_counts_follow_the_algorithm():
     mean = bench._weighted(g, bench.valu_ops_per_attempt)
     lo, hi = bench.valu_ops_per_attempt(2, 0.25), bench.valu_ops_per_attempt(3, 0.03)
     assert min(lo, hi) < mean < max(lo, hi)
+
+
+def test_bench_record_of_a_large_3d_run():
+    """The JSON record of a timed run, from the figures of a driver-style run
+    on the large 3D workload (20 steps of 2388.83 ms, sweep launch 2387.30 ms,
+    456.20 counter bytes per attempt): the contract's keys, the value, the
+    roofline against HBM and the moved bytes against the random-line ceiling."""
+    import json
+    groups = [(3, 48, 3318, 16384)]
+    per_step = 16384 * 16 * 48 ** 3
+    r = bench.bench_record("large_3d", groups, 16, 20, 5, 20 * 2.38883436185, 2387.30303955,
+                           2, False, False, 234881024, None, 456.2014152849162 * per_step)
+    json.dumps(r)
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config"):
+        assert k in r, k
+    assert r["config"]["workload"] == "large_3d" and r["config"]["attempts_per_step"] == per_step
+    assert abs(r["value"] / 1.2136056694e10 - 1) < 1e-9
+    assert abs(r["ms_per_step"] - 2388.83436185) < 1e-6
+    roof = r["roofline"]
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
+    assert abs(roof["frac"] - 0.0912666) < 1e-6
+    assert abs(roof["achieved"] / roof["peak"] - roof["frac"]) < 1e-12
+    assert abs(roof["traffic_per_attempt"] - 456.2014152849162) < 1e-9
+    assert abs(roof["moved"]["frac_of_random_line_peak"] - 0.84195) < 1e-4
+    assert roof["lds"]["frac"] == 0.0 and abs(roof["valu"]["frac"] - 0.0661220) < 1e-6
+    assert abs(r["sweep_attempts_per_s"] * 2.38730303955 - per_step) < 1.0
+
+
+def test_bench_record_with_state_in_lds():
+    """LDS-resident walker state: bound by the VALU, no HBM or moved entry."""
+    groups = [(2, 64, 205, 4096)]
+    r = bench.bench_record("x", groups, 100, 3, 1, 3.0, 900.0, 5, True, True, 0, [0.0], None)
+    roof = r["roofline"]
+    assert roof["bound"] == "alu" and roof["traffic"] is None and "moved" not in roof
+    assert roof["hbm"]["frac"] == 0.0 and roof["lds"]["frac"] > 0.0
+    assert abs(roof["frac"] - roof["valu"]["frac"]) < 1e-15
