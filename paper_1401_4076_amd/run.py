@@ -178,7 +178,8 @@ def main(argv=None):
     elif args.net:
         from paper_1401_4076_amd import learned as LR
         t0 = time.perf_counter()
-        net = M.Mlp(16384)
+        rows = max(hi - lo + 1 for lo, hi, _ in (ctx.window(g) for g in range(ctx.ngroups)))
+        net = M.Mlp(max(16384, rows))
         net.set_params(np.load(args.net, allow_pickle=False).astype(np.float32))
         lnW = LR.predict(net, ctx)  # synchronised
         net.close()
