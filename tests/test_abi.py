@@ -89,3 +89,14 @@ def test_null_arguments_rejected():
 def test_default_window_matches_oracle(d, L, Ns):
     for N in Ns:
         assert M.mucaDefaultWindow(d, L, N) == (O.energy_floor(d, L, N), 0), (d, L, N)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without libmuca.so every call raises ImportError, and a
+    context cannot be created."""
+    monkeypatch.setattr(M, "LIB_PATH", str(tmp_path / "libmuca.so"))
+    monkeypatch.setattr(M, "_lib", None)
+    with pytest.raises(ImportError, match="not built"):
+        M.lib()
+    with pytest.raises(ImportError):
+        M.Context([(2, 8, 16, 4)], seed=1)
