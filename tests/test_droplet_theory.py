@@ -97,3 +97,18 @@ def test_measured_fraction_reads_the_droplet_as_liquid(d):
     # a droplet of volume V_L at the liquid density holds the whole excess
     assert T.measured_fraction(d, VL * (1 - p["rho0"]), N, L, p["rho0"]) == pytest.approx(1.0)
     assert T.measured_fraction(d, 0, N, L, p["rho0"]) == 0.0
+
+
+def test_table1_constants_follow_their_stated_origins():
+    """Table 1 re-derived from how Sec. 4 says its values were obtained, so a
+    mistyped constant fails: the lattice-gas temperature is the Ising one over
+    4 (T^I = 1.5 in 2D, 2 in 3D); in 2D the background density is
+    rho0 = (1 - m0) / 2 with the Ising spontaneous magnetisation, here Yang's
+    exact m0 = (1 - sinh(2 / T^I)^-4)^(1/8) (0.0067502 against the printed
+    0.00675); in 3D tau_W = 6 sigma / 4 with the interface tension
+    sigma = 1.9072 of the low-temperature series (2.8608, printed ~2.861)."""
+    P = T.PARAMS
+    assert P[2]["T"] == 1.5 / 4 and P[3]["T"] == 2.0 / 4
+    m0 = (1.0 - np.sinh(2.0 / 1.5) ** -4) ** 0.125
+    assert abs((1.0 - m0) / 2.0 - P[2]["rho0"]) < 5e-7
+    assert abs(6.0 * 1.9072 / 4.0 - P[3]["tau_w"]) < 5e-4
