@@ -112,3 +112,23 @@ def test_table1_constants_follow_their_stated_origins():
     m0 = (1.0 - np.sinh(2.0 / 1.5) ** -4) ** 0.125
     assert abs((1.0 - m0) / 2.0 - P[2]["rho0"]) < 5e-7
     assert abs(6.0 * 1.9072 / 4.0 - P[3]["tau_w"]) < 5e-4
+
+
+def test_table1_2d_surface_free_energy_from_the_exact_crystal_shape():
+    """The 2D tau_W of Table 1 (1.06125), rescaled like the temperature
+    (Sec. 4: tau_W = tau_W^I / 4), from the exact equilibrium crystal shape of
+    the square-lattice Ising model at T^I = 1.5 (J = 1): the Wulff shape
+    W = {cosh(x / T) + cosh(y / T) <= cosh(2 / T) coth(2 / T)} (Rottman and
+    Wortis; Avron, van Beijeren, Schulman and Zia), whose half-width on an
+    axis is Onsager's interface tension 2 + T ln tanh(1 / T); by Wulff's
+    theorem the least boundary free energy of a droplet of area V is
+    2 sqrt(|W| V), so tau_W^I = 2 sqrt(|W|)."""
+    from scipy import integrate
+    TI = 1.5
+    C = np.cosh(2.0 / TI) / np.tanh(2.0 / TI)
+    half = np.arccosh(C - 1.0) * TI
+    assert abs(half - (2.0 + TI * np.log(np.tanh(1.0 / TI)))) < 1e-12
+    area, _ = integrate.quad(
+        lambda x: 2.0 * TI * np.arccosh(max(1.0, C - np.cosh(x / TI))), -half, half, limit=200)
+    tau_w = 2.0 * np.sqrt(area) / 4.0
+    assert abs(tau_w - T.PARAMS[2]["tau_w"]) < 2e-4  # 1.061353 against 1.06125
